@@ -1,0 +1,582 @@
+// C ABI of the library: symbolic analysis on the host, numeric factorization,
+// refactorization and solve on the device (see include/basker.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/basker.h"
+#include "device.hpp"
+#include "symbolic.hpp"
+
+using namespace basker;
+
+namespace {
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  int64_t cap = 0;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  hipError_t reserve(int64_t n) {
+    if (n <= cap && p) return hipSuccess;
+    release();
+    int64_t m = n > 0 ? n : 1;
+    hipError_t e = hipMalloc((void**)&p, sizeof(T) * (size_t)m);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    cap = m;
+    return hipSuccess;
+  }
+  hipError_t upload(const std::vector<T>& v, hipStream_t s) {
+    hipError_t e = reserve((int64_t)v.size());
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
+  }
+};
+
+}  // namespace
+
+struct basker_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  basker_options opt{};
+  Plan plan;
+  std::string err;
+  // plan on device
+  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, parent, nchild, ready;
+  DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, bdep_cnt, bdep_ptr, bdep_idx, bready;
+  std::vector<int32_t> h_bready;
+  // numeric state
+  DBuf<double> vals, Rx, OTx;
+  DBuf<int32_t> done, queue, ctrs, pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
+  DBuf<int32_t> Li, Ui;
+  DBuf<double> Lx, Ux;
+  DBuf<unsigned long long> pool;
+  DBuf<char> gws;
+  int64_t gws_stride = 0;
+  int gws_slots = 0;
+  int grid = 0;
+  // solve scratch
+  DBuf<int32_t> bdone, bqueue, bctrs, sstatus;
+  DBuf<double> W, Z, Bdev;
+  bool factored = false;
+  int64_t lnz = 0, unz = 0;
+  hipEvent_t ev[6] = {};
+  basker_info_t info{};
+};
+
+static basker_status fail(basker_ctx* h, basker_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+static basker_status hip_fail(basker_ctx* h, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  if (h) h->err = m;
+  return e == hipErrorOutOfMemory ? BASKER_ERR_OOM : BASKER_ERR_DEVICE;
+}
+
+#define HIPCHK(h, expr)                                   \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return hip_fail((h), _e, #expr); \
+  } while (0)
+
+extern "C" basker_status basker_default_options(basker_options* o) {
+  if (!o) return BASKER_ERR_INVALID;
+  std::memset(o, 0, sizeof(*o));
+  o->pivot_tol = 1e-3;
+  o->diag_pref = 1;
+  o->matching = 1;
+  o->btf = 1;
+  o->fill_order = 1;
+  o->nd_leaves = 16;
+  o->nd_min_block = 10000;
+  o->capacity_factor = 6.0;
+  o->device = 0;
+  o->stream = nullptr;
+  return BASKER_OK;
+}
+
+extern "C" const char* basker_status_string(basker_status s) {
+  switch (s) {
+    case BASKER_OK: return "ok";
+    case BASKER_REFACTOR_FELL_BACK: return "refactor fell back to a full factorization";
+    case BASKER_ERR_INVALID: return "invalid input";
+    case BASKER_ERR_STRUCT_SINGULAR: return "structurally singular";
+    case BASKER_ERR_NUM_SINGULAR: return "numerically singular";
+    case BASKER_ERR_OOM: return "out of memory";
+    case BASKER_ERR_PATTERN: return "no factorization to reuse";
+    case BASKER_ERR_DEVICE: return "device error";
+    case BASKER_ERR_WORKSPACE: return "column pattern exceeds the workspace";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* basker_last_error(basker_handle h) { return h ? h->err.c_str() : ""; }
+
+// Everything the device needs from the plan, plus the solve's row-wise coupling and
+// block dependency lists.
+static basker_status upload_plan(basker_ctx* h) {
+  Plan& P = h->plan;
+  const int n = P.n;
+  hipStream_t s = h->stream;
+  std::vector<int32_t> glo(n), ghi(n);
+  for (size_t g = 0; g + 1 < P.grpptr.size(); g++)
+    for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) { glo[k] = P.grpptr[g]; ghi[k] = P.grpptr[g + 1]; }
+  // off-diagonal part by row (CSR), columns ascending inside each row
+  std::vector<int32_t> OTp(n + 1, 0), OTj(P.Oi.size()), OTmap(P.Oi.size());
+  for (size_t q = 0; q < P.Oi.size(); q++) OTp[P.Oi[q] + 1]++;
+  for (int i = 0; i < n; i++) OTp[i + 1] += OTp[i];
+  {
+    std::vector<int32_t> fillp(OTp.begin(), OTp.end() - 1);
+    for (int k = 0; k < n; k++)
+      for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) {
+        int32_t i = P.Oi[q];
+        OTj[fillp[i]] = k;
+        OTmap[fillp[i]] = P.Omap[q];
+        fillp[i]++;
+      }
+  }
+  // block dependencies: block b reads z of later blocks c; dependents of c are b
+  const int nb = (int)P.blkptr.size() - 1;
+  std::vector<int32_t> blk(n);
+  for (int b = 0; b < nb; b++)
+    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk[k] = b;
+  std::vector<int32_t> bcnt(nb, 0), bptr(nb + 1, 0), bidx;
+  std::vector<std::pair<int32_t, int32_t>> edges;  // (c, b)
+  {
+    std::vector<int32_t> seen(nb, -1);
+    for (int b = 0; b < nb; b++) {
+      for (int i = P.blkptr[b]; i < P.blkptr[b + 1]; i++)
+        for (int32_t q = OTp[i]; q < OTp[i + 1]; q++) {
+          int c = blk[OTj[q]];
+          if (seen[c] != b) { seen[c] = b; bcnt[b]++; edges.push_back({c, b}); }
+        }
+    }
+  }
+  for (auto& e : edges) bptr[e.first + 1]++;
+  for (int c = 0; c < nb; c++) bptr[c + 1] += bptr[c];
+  bidx.resize(edges.size());
+  {
+    std::vector<int32_t> fp(bptr.begin(), bptr.end() - 1);
+    for (auto& e : edges) bidx[fp[e.first]++] = e.second;
+  }
+  h->h_bready.clear();
+  for (int b = nb - 1; b >= 0; b--)
+    if (bcnt[b] == 0) h->h_bready.push_back(b);
+  // sizes > 0 for every buffer
+  HIPCHK(h, h->Rp.upload(P.Rp, s));
+  HIPCHK(h, h->Ri.upload(P.Ri, s));
+  HIPCHK(h, h->Rmap.upload(P.Rmap, s));
+  HIPCHK(h, h->grp_lo.upload(glo, s));
+  HIPCHK(h, h->grp_hi.upload(ghi, s));
+  HIPCHK(h, h->parent.upload(P.parent, s));
+  HIPCHK(h, h->nchild.upload(P.nchild, s));
+  HIPCHK(h, h->ready.upload(P.ready, s));
+  HIPCHK(h, h->OTp.upload(OTp, s));
+  HIPCHK(h, h->OTj.upload(OTj, s));
+  HIPCHK(h, h->OTmap.upload(OTmap, s));
+  HIPCHK(h, h->prow.upload(P.prow, s));
+  HIPCHK(h, h->qcol.upload(P.qcol, s));
+  HIPCHK(h, h->blkptr.upload(P.blkptr, s));
+  HIPCHK(h, h->bdep_cnt.upload(bcnt, s));
+  HIPCHK(h, h->bdep_ptr.upload(bptr, s));
+  HIPCHK(h, h->bdep_idx.upload(bidx, s));
+  HIPCHK(h, h->bready.upload(h->h_bready, s));
+  const int64_t nnzd = (int64_t)P.Ri.size();
+  HIPCHK(h, h->vals.reserve(P.nnz));
+  HIPCHK(h, h->Rx.reserve(nnzd));
+  HIPCHK(h, h->OTx.reserve((int64_t)OTj.size()));
+  HIPCHK(h, h->done.reserve(n));
+  HIPCHK(h, h->queue.reserve(n));
+  HIPCHK(h, h->ctrs.reserve(4));
+  HIPCHK(h, h->pinv.reserve(n));
+  HIPCHK(h, h->piv.reserve(n));
+  HIPCHK(h, h->Lbeg.reserve(n));
+  HIPCHK(h, h->Lcnt.reserve(n));
+  HIPCHK(h, h->Ubeg.reserve(n));
+  HIPCHK(h, h->Ucnt.reserve(n));
+  HIPCHK(h, h->status.reserve(ST_WORDS));
+  HIPCHK(h, h->pool.reserve(2));
+  HIPCHK(h, h->bdone.reserve(nb));
+  HIPCHK(h, h->bqueue.reserve(nb));
+  HIPCHK(h, h->bctrs.reserve(4));
+  HIPCHK(h, h->sstatus.reserve(4));
+  // L/U pools
+  double cf = h->opt.capacity_factor > 0 ? h->opt.capacity_factor : 6.0;
+  int64_t cap = (int64_t)(cf * (double)nnzd) + n + 64;
+  if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+  HIPCHK(h, h->Li.reserve(cap));
+  HIPCHK(h, h->Lx.reserve(cap));
+  HIPCHK(h, h->Ui.reserve(cap));
+  HIPCHK(h, h->Ux.reserve(cap));
+  // persistent grid and the global fallback workspace (one region per workgroup)
+  int grid = std::min(n > 0 ? n : 1, kNumCu * kWavesPerCu);
+  h->grid = grid;
+  h->gws_slots = 1 << 14;
+  h->gws_stride = ((48LL * h->gws_slots + 16 + 255) / 256) * 256;
+  HIPCHK(h, h->gws.reserve(h->gws_stride * grid));
+  HIPCHK(h, hipMemsetAsync(h->gws.p, 0xff, (size_t)(h->gws_stride * grid), s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return BASKER_OK;
+}
+
+static basker_status make_handle(const basker_options* o, basker_handle* out, basker_ctx** ph) {
+  if (!out) return BASKER_ERR_INVALID;
+  *out = nullptr;
+  basker_ctx* h = new (std::nothrow) basker_ctx();
+  if (!h) return BASKER_ERR_OOM;
+  if (o) h->opt = *o; else basker_default_options(&h->opt);
+  h->device = h->opt.device;
+  if (h->device < 0) {  // analysis only: no device work
+    *ph = h;
+    return BASKER_OK;
+  }
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) { delete h; return BASKER_ERR_DEVICE; }
+  if (h->opt.stream) {
+    h->stream = (hipStream_t)h->opt.stream;
+  } else {
+    e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete h; return BASKER_ERR_DEVICE; }
+    h->own_stream = true;
+  }
+  for (auto& ev : h->ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) { basker_free(h); return BASKER_ERR_DEVICE; }
+  }
+  *ph = h;
+  return BASKER_OK;
+}
+
+static void fill_info_static(basker_ctx* h) {
+  const Plan& P = h->plan;
+  basker_info_t& I = h->info;
+  I.n = P.n;
+  I.nnz = P.nnz;
+  I.nnz_diag = (int64_t)P.Ri.size();
+  I.nnz_offdiag = (int64_t)P.Oi.size();
+  I.nblocks = (int32_t)P.blkptr.size() - 1;
+  I.ngroups = (int32_t)P.grpptr.size() - 1;
+  I.struct_rank = P.struct_rank;
+  I.max_depth = P.max_depth;
+  I.bottleneck = P.bottleneck;
+  I.nd_blocks = P.n_nd_blocks;
+  I.fail_col = -1;
+}
+
+extern "C" basker_status basker_symbolic(int32_t n, const int32_t* colptr, const int32_t* rowind, const double* values,
+                                         const basker_options* o, basker_handle* out) {
+  if (!colptr || (n > 0 && !rowind) || !out) return BASKER_ERR_INVALID;
+  basker_ctx* h = nullptr;
+  basker_status st = make_handle(o, out, &h);
+  if (st != BASKER_OK) return st;
+  SymbolicOptions so;
+  so.matching = h->opt.matching;
+  so.btf = h->opt.btf;
+  so.fill_order = h->opt.fill_order;
+  so.nd_leaves = h->opt.nd_leaves;
+  so.nd_min_block = h->opt.nd_min_block;
+  int rc = build_plan(n, colptr, rowind, values, so, h->plan);
+  if (rc != 0) {
+    basker_status s = rc == -2 ? BASKER_ERR_STRUCT_SINGULAR : BASKER_ERR_INVALID;
+    std::string m = h->plan.error;
+    basker_free(h);
+    (void)m;
+    return s;
+  }
+  if (h->device >= 0) {
+    st = upload_plan(h);
+    if (st != BASKER_OK) { basker_free(h); return st; }
+  }
+  fill_info_static(h);
+  *out = h;
+  return BASKER_OK;
+}
+
+extern "C" basker_status basker_symbolic_ordered(int32_t n, const int32_t* colptr, const int32_t* rowind,
+                                                 const int32_t* prow, const int32_t* qcol, int32_t nblocks,
+                                                 const int32_t* blkptr, int32_t ngroups, const int32_t* grpptr,
+                                                 const basker_options* o, basker_handle* out) {
+  if (!colptr || (n > 0 && (!rowind || !prow || !qcol)) || !blkptr || !grpptr || !out) return BASKER_ERR_INVALID;
+  basker_ctx* h = nullptr;
+  basker_status st = make_handle(o, out, &h);
+  if (st != BASKER_OK) return st;
+  int rc = build_plan_user(n, colptr, rowind, prow, qcol, nblocks, blkptr, ngroups, grpptr, h->plan);
+  if (rc != 0) { basker_free(h); return BASKER_ERR_INVALID; }
+  if (h->device >= 0) {
+    st = upload_plan(h);
+    if (st != BASKER_OK) { basker_free(h); return st; }
+  }
+  fill_info_static(h);
+  *out = h;
+  return BASKER_OK;
+}
+
+static FactorArgs factor_args(basker_ctx* h, int refactor) {
+  FactorArgs a{};
+  a.n = h->plan.n;
+  a.Rp = h->Rp.p; a.Ri = h->Ri.p; a.Rx = h->Rx.p;
+  a.grp_lo = h->grp_lo.p; a.grp_hi = h->grp_hi.p;
+  a.parent = h->parent.p; a.nchild = h->nchild.p;
+  a.done = h->done.p; a.queue = h->queue.p; a.ctrs = h->ctrs.p;
+  a.pinv = h->pinv.p; a.piv = h->piv.p;
+  a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p;
+  a.Li = h->Li.p; a.Lx = h->Lx.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
+  a.pool_next = h->pool.p;
+  a.Lcap = h->Li.cap; a.Ucap = h->Ui.cap;
+  a.status = h->status.p;
+  a.tau = h->opt.pivot_tol;
+  a.diag_pref = h->opt.diag_pref;
+  a.refactor = refactor;
+  a.gws = h->gws.p; a.gws_stride = h->gws_stride; a.gws_slots = h->gws_slots;
+  return a;
+}
+
+// values -> device copy (if on host) -> scattered into R's block storage
+static basker_status stage_values(basker_ctx* h, const double* values, int32_t on_device) {
+  const double* dv = values;
+  hipStream_t s = h->stream;
+  if (!on_device) {
+    if (h->plan.nnz > 0)
+      HIPCHK(h, hipMemcpyAsync(h->vals.p, values, sizeof(double) * (size_t)h->plan.nnz, hipMemcpyHostToDevice, s));
+    dv = h->vals.p;
+  }
+  HIPCHK(h, hipEventRecord(h->ev[4], s));
+  HIPCHK(h, launch_scatter(dv, h->Rmap.p, h->Rx.p, (int64_t)h->plan.Ri.size(), s));
+  HIPCHK(h, launch_scatter(dv, h->OTmap.p, h->OTx.p, (int64_t)h->plan.Oi.size(), s));
+  HIPCHK(h, hipEventRecord(h->ev[5], s));
+  return BASKER_OK;
+}
+
+// one device pass; fills st[ST_WORDS] and the pool counters
+static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st, unsigned long long* poolc) {
+  hipStream_t s = h->stream;
+  FactorArgs a = factor_args(h, refactor);
+  HIPCHK(h, launch_factor_init(a, h->ready.p, (int32_t)h->plan.ready.size(), s));
+  HIPCHK(h, hipEventRecord(h->ev[0], s));
+  HIPCHK(h, launch_factor(a, h->grid, s));
+  HIPCHK(h, hipEventRecord(h->ev[1], s));
+  HIPCHK(h, hipMemcpyAsync(st, h->status.p, sizeof(int32_t) * ST_WORDS, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(poolc, h->pool.p, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->info.factor_kernel_ms = ms;
+  if (hipEventElapsedTime(&ms, h->ev[4], h->ev[5]) == hipSuccess) h->info.scatter_kernel_ms = ms;
+  return BASKER_OK;
+}
+
+static basker_status do_factor(basker_ctx* h) {
+  for (int attempt = 0; attempt < 8; attempt++) {
+    int32_t st[ST_WORDS];
+    unsigned long long poolc[2];
+    basker_status r = run_factor_kernel(h, 0, st, poolc);
+    if (r != BASKER_OK) return r;
+    h->info.fail_col = st[ST_FAILCOL] == 0x7fffffff ? -1 : st[ST_FAILCOL];
+    if (st[ST_CODE] == DEV_OK) {
+      h->lnz = (int64_t)poolc[0];
+      h->unz = (int64_t)poolc[1];
+      h->info.lnz = h->lnz;
+      h->info.unz = h->unz;
+      h->info.offdiag_pivots = st[ST_OFFDIAG];
+      h->factored = true;
+      h->info.factor_calls++;
+      return BASKER_OK;
+    }
+    h->factored = false;
+    if (st[ST_CODE] == DEV_POOL) {
+      // grow to twice the demand seen so far
+      int64_t need = std::max<int64_t>((int64_t)std::max(poolc[0], poolc[1]) * 2, 2 * h->Li.cap);
+      if (need > 0x7fffffffLL) need = 0x7fffffffLL;
+      if (need <= h->Li.cap) return fail(h, BASKER_ERR_OOM, "L/U pool exceeds 2^31 entries");
+      HIPCHK(h, h->Li.reserve(need));
+      HIPCHK(h, h->Lx.reserve(need));
+      HIPCHK(h, h->Ui.reserve(need));
+      HIPCHK(h, h->Ux.reserve(need));
+      h->info.pool_regrows++;
+      continue;
+    }
+    if (st[ST_CODE] == DEV_SINGULAR)
+      return fail(h, BASKER_ERR_NUM_SINGULAR, "numerically singular at column " + std::to_string(h->info.fail_col));
+    if (st[ST_CODE] == DEV_WORKSPACE)
+      return fail(h, BASKER_ERR_WORKSPACE, "column pattern exceeds the workspace at column " + std::to_string(h->info.fail_col));
+    return fail(h, BASKER_ERR_DEVICE, "factor kernel status " + std::to_string(st[ST_CODE]));
+  }
+  return fail(h, BASKER_ERR_OOM, "L/U pool growth did not converge");
+}
+
+extern "C" basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device) {
+  if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
+  if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
+  HIPCHK(h, hipSetDevice(h->device));
+  basker_status r = stage_values(h, values, values_on_device);
+  if (r != BASKER_OK) return r;
+  return do_factor(h);
+}
+
+extern "C" basker_status basker_refactor(basker_handle h, const double* values, int32_t values_on_device) {
+  if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
+  if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
+  if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "refactor before a successful factor");
+  HIPCHK(h, hipSetDevice(h->device));
+  basker_status r = stage_values(h, values, values_on_device);
+  if (r != BASKER_OK) return r;
+  int32_t st[ST_WORDS];
+  unsigned long long poolc[2];
+  r = run_factor_kernel(h, 1, st, poolc);
+  if (r != BASKER_OK) return r;
+  h->info.refactor_calls++;
+  if (st[ST_CODE] == DEV_OK) return BASKER_OK;
+  h->info.fail_col = st[ST_FAILCOL] == 0x7fffffff ? -1 : st[ST_FAILCOL];
+  if (st[ST_CODE] == DEV_REFACTOR_FAIL || st[ST_CODE] == DEV_WORKSPACE) {
+    h->info.refactor_fallbacks++;
+    r = do_factor(h);
+    return r == BASKER_OK ? BASKER_REFACTOR_FELL_BACK : r;
+  }
+  h->factored = false;
+  return fail(h, BASKER_ERR_DEVICE, "refactor kernel status " + std::to_string(st[ST_CODE]));
+}
+
+extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb, int32_t B_on_device) {
+  if (!h || nrhs < 0 || (nrhs > 0 && !B) || ldb < h->plan.n) return BASKER_ERR_INVALID;
+  if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "solve before a successful factor");
+  if (nrhs == 0 || h->plan.n == 0) return BASKER_OK;
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  const int n = h->plan.n;
+  const int64_t tot = (int64_t)n * nrhs;
+  HIPCHK(h, h->W.reserve(tot));
+  HIPCHK(h, h->Z.reserve(tot));
+  double* dB = B;
+  int32_t ld = ldb;
+  if (!B_on_device) {
+    HIPCHK(h, h->Bdev.reserve(tot));
+    HIPCHK(h, hipMemcpy2DAsync(h->Bdev.p, sizeof(double) * n, B, sizeof(double) * (size_t)ldb, sizeof(double) * n,
+                               nrhs, hipMemcpyHostToDevice, s));
+    dB = h->Bdev.p;
+    ld = n;
+  }
+  SolveArgs a{};
+  a.n = n;
+  a.nblk = (int32_t)h->plan.blkptr.size() - 1;
+  a.nrhs = nrhs;
+  a.ldb = ld;
+  a.blkptr = h->blkptr.p;
+  a.piv = h->piv.p;
+  a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Li = h->Li.p; a.Lx = h->Lx.p;
+  a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
+  a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
+  a.bdep_cnt = h->bdep_cnt.p; a.bdep_ptr = h->bdep_ptr.p; a.bdep_idx = h->bdep_idx.p;
+  a.bdone = h->bdone.p; a.queue = h->bqueue.p; a.ctrs = h->bctrs.p; a.status = h->sstatus.p;
+  a.prow = h->prow.p; a.qcol = h->qcol.p;
+  a.B = dB; a.W = h->W.p; a.Z = h->Z.p;
+  const int grid = std::min(a.nblk, kNumCu * kWavesPerCu);
+  HIPCHK(h, hipEventRecord(h->ev[2], s));
+  HIPCHK(h, launch_solve(a, h->bready.p, (int32_t)h->h_bready.size(), grid, s));
+  HIPCHK(h, hipEventRecord(h->ev[3], s));
+  if (!B_on_device)
+    HIPCHK(h, hipMemcpy2DAsync(B, sizeof(double) * (size_t)ldb, h->Bdev.p, sizeof(double) * n, sizeof(double) * n,
+                               nrhs, hipMemcpyDeviceToHost, s));
+  int32_t sst = 0;
+  HIPCHK(h, hipMemcpyAsync(&sst, h->sstatus.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve kernel stalled");
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev[2], h->ev[3]) == hipSuccess) h->info.solve_kernel_ms = ms;
+  return BASKER_OK;
+}
+
+extern "C" basker_status basker_info(basker_handle h, basker_info_t* info) {
+  if (!h || !info) return BASKER_ERR_INVALID;
+  *info = h->info;
+  return BASKER_OK;
+}
+
+extern "C" basker_status basker_get_ordering(basker_handle h, int32_t* prow, int32_t* qcol, int32_t* blkptr,
+                                             int32_t* grpptr, int32_t* grpparent) {
+  if (!h) return BASKER_ERR_INVALID;
+  const Plan& P = h->plan;
+  if (prow) std::copy(P.prow.begin(), P.prow.end(), prow);
+  if (qcol) std::copy(P.qcol.begin(), P.qcol.end(), qcol);
+  if (blkptr) std::copy(P.blkptr.begin(), P.blkptr.end(), blkptr);
+  if (grpptr) std::copy(P.grpptr.begin(), P.grpptr.end(), grpptr);
+  if (grpparent) std::copy(P.grp_parent.begin(), P.grp_parent.end(), grpparent);
+  return BASKER_OK;
+}
+
+extern "C" basker_status basker_extract(basker_handle h, int32_t* piv, int64_t* Lp, int32_t* Li, double* Lx,
+                                        int64_t* Up, int32_t* Ui, double* Ux) {
+  if (!h) return BASKER_ERR_INVALID;
+  if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "extract before a successful factor");
+  HIPCHK(h, hipSetDevice(h->device));
+  const int n = h->plan.n;
+  hipStream_t s = h->stream;
+  std::vector<int32_t> hpiv(n), lb(n), lc(n), ubg(n), ucn(n);
+  std::vector<int32_t> li(h->lnz), ui(h->unz);
+  std::vector<double> lx(h->lnz), ux(h->unz);
+  if (n > 0) {
+    HIPCHK(h, hipMemcpyAsync(hpiv.data(), h->piv.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(lb.data(), h->Lbeg.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(lc.data(), h->Lcnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(ubg.data(), h->Ubeg.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(ucn.data(), h->Ucnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  }
+  if (h->lnz > 0) {
+    HIPCHK(h, hipMemcpyAsync(li.data(), h->Li.p, sizeof(int32_t) * h->lnz, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(lx.data(), h->Lx.p, sizeof(double) * h->lnz, hipMemcpyDeviceToHost, s));
+  }
+  if (h->unz > 0) {
+    HIPCHK(h, hipMemcpyAsync(ui.data(), h->Ui.p, sizeof(int32_t) * h->unz, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(ux.data(), h->Ux.p, sizeof(double) * h->unz, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  std::vector<int32_t> pinv(n, -1);
+  for (int k = 0; k < n; k++) pinv[hpiv[k]] = k;
+  if (piv) std::copy(hpiv.begin(), hpiv.end(), piv);
+  std::vector<std::pair<int32_t, double>> tmp;
+  int64_t lo = 0, uo = 0;
+  if (Lp) Lp[0] = 0;
+  if (Up) Up[0] = 0;
+  for (int k = 0; k < n; k++) {
+    tmp.clear();
+    for (int t = 0; t < lc[k]; t++) tmp.push_back({pinv[li[lb[k] + t]], lx[lb[k] + t]});
+    std::sort(tmp.begin(), tmp.end(), [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+      return x.first < y.first;
+    });
+    for (auto& e : tmp) {
+      if (Li) Li[lo] = e.first;
+      if (Lx) Lx[lo] = e.second;
+      lo++;
+    }
+    if (Lp) Lp[k + 1] = lo;
+    for (int t = 0; t < ucn[k]; t++) {
+      if (Ui) Ui[uo] = ui[ubg[k] + t];
+      if (Ux) Ux[uo] = ux[ubg[k] + t];
+      uo++;
+    }
+    if (Up) Up[k + 1] = uo;
+  }
+  return BASKER_OK;
+}
+
+extern "C" void basker_free(basker_handle h) {
+  if (!h) return;
+  if (h->device < 0) { delete h; return; }
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& ev : h->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}

@@ -1,0 +1,794 @@
+// Host-side symbolic analysis (see symbolic.hpp).
+#include "symbolic.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace basker {
+
+namespace {
+
+bool validate_csc(int n, const int32_t* Ap, const int32_t* Ai, std::string& err) {
+  if (n < 0) { err = "negative order"; return false; }
+  if (Ap[0] != 0) { err = "colptr[0] != 0"; return false; }
+  for (int j = 0; j < n; j++) {
+    if (Ap[j + 1] < Ap[j]) { err = "colptr not monotone"; return false; }
+    for (int32_t p = Ap[j]; p < Ap[j + 1]; p++) {
+      if (Ai[p] < 0 || Ai[p] >= n) { err = "row index out of range"; return false; }
+      if (p > Ap[j] && Ai[p] <= Ai[p - 1]) { err = "rows not sorted/unique"; return false; }
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Maximum matching by depth-first augmenting paths with a cheap-assignment
+// lookahead (Duff's MC21 scheme).  Entries with |a| < thresh are not usable.
+// ---------------------------------------------------------------------------
+int max_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax, double thresh,
+                 std::vector<int32_t>& m) {
+  auto usable = [&](int32_t p) { return !Ax || std::fabs(Ax[p]) >= thresh; };
+  std::vector<int32_t> col_of_row(n, -1), cheap(n), visited(n, -1), cstack(n), pos(n);
+  if ((int)m.size() != n) m.assign(n, -1);
+  int matched = 0;
+  for (int j = 0; j < n; j++) {
+    int32_t i = m[j];
+    bool ok = false;
+    if (i >= 0) {
+      for (int32_t p = Ap[j]; p < Ap[j + 1]; p++)
+        if (Ai[p] == i) { ok = usable(p) && col_of_row[i] < 0; break; }
+    }
+    if (ok) { col_of_row[i] = j; matched++; } else m[j] = -1;
+  }
+  for (int j = 0; j < n; j++) cheap[j] = Ap[j];
+  for (int j0 = 0; j0 < n; j0++) {
+    if (m[j0] >= 0) continue;
+    int head = 0;
+    cstack[0] = j0;
+    pos[j0] = Ap[j0];
+    visited[j0] = j0;
+    int32_t found = -1;
+    while (head >= 0) {
+      int32_t j = cstack[head];
+      for (; cheap[j] < Ap[j + 1]; cheap[j]++) {
+        int32_t p = cheap[j];
+        if (usable(p) && col_of_row[Ai[p]] < 0) { found = Ai[p]; break; }
+      }
+      if (found >= 0) break;
+      bool pushed = false;
+      for (int32_t p = pos[j]; p < Ap[j + 1]; p++) {
+        if (!usable(p)) continue;
+        int32_t jj = col_of_row[Ai[p]];
+        if (jj >= 0 && visited[jj] != j0) {
+          pos[j] = p + 1;
+          visited[jj] = j0;
+          pos[jj] = Ap[jj];
+          cstack[++head] = jj;
+          pushed = true;
+          break;
+        }
+      }
+      if (!pushed) { pos[j] = Ap[j + 1]; head--; }
+    }
+    if (found >= 0) {
+      int32_t r = found;
+      for (int h = head; h >= 0; h--) {
+        int32_t c = cstack[h];
+        int32_t old = m[c];
+        m[c] = r;
+        col_of_row[r] = c;
+        r = old;
+      }
+      matched++;
+    }
+  }
+  return matched;
+}
+
+// Bottleneck matching: a perfect matching maximising min |a(m[j], j)| (the MC64
+// bottleneck objective), by bisection over the distinct magnitudes with a warm start.
+int bottleneck_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
+                        std::vector<int32_t>& m, double* bottleneck) {
+  m.assign(n, -1);
+  int r = max_matching(n, Ap, Ai, nullptr, 0.0, m);
+  if (r < n) { if (bottleneck) *bottleneck = 0.0; return r; }
+  if (!Ax || n == 0) { if (bottleneck) *bottleneck = 0.0; return n; }
+  // upper bound: every column and every row must keep one usable entry
+  double ub = INFINITY;
+  std::vector<double> rowmax(n, 0.0);
+  for (int j = 0; j < n; j++) {
+    double cm = 0.0;
+    for (int32_t p = Ap[j]; p < Ap[j + 1]; p++) {
+      double v = std::fabs(Ax[p]);
+      cm = std::max(cm, v);
+      rowmax[Ai[p]] = std::max(rowmax[Ai[p]], v);
+    }
+    ub = std::min(ub, cm);
+  }
+  for (int i = 0; i < n; i++) ub = std::min(ub, rowmax[i]);
+  std::vector<double> mags;
+  mags.reserve(Ap[n]);
+  for (int32_t p = 0; p < Ap[n]; p++) {
+    double v = std::fabs(Ax[p]);
+    if (v <= ub) mags.push_back(v);
+  }
+  std::sort(mags.begin(), mags.end());
+  mags.erase(std::unique(mags.begin(), mags.end()), mags.end());
+  // current matching is feasible at the smallest magnitude
+  double best = INFINITY;
+  for (int j = 0; j < n; j++)
+    for (int32_t p = Ap[j]; p < Ap[j + 1]; p++)
+      if (Ai[p] == m[j]) best = std::min(best, std::fabs(Ax[p]));
+  int lo = (int)(std::lower_bound(mags.begin(), mags.end(), best) - mags.begin());
+  if (lo >= (int)mags.size()) lo = (int)mags.size() - 1;
+  int hi = (int)mags.size() - 1;
+  std::vector<int32_t> trial;
+  while (lo < hi) {
+    int mid = lo + (hi - lo + 1) / 2;
+    trial = m;
+    if (max_matching(n, Ap, Ai, Ax, mags[mid], trial) == n) { lo = mid; m.swap(trial); }
+    else hi = mid - 1;
+  }
+  if (bottleneck) {
+    double b = INFINITY;
+    for (int j = 0; j < n; j++)
+      for (int32_t p = Ap[j]; p < Ap[j + 1]; p++)
+        if (Ai[p] == m[j]) b = std::min(b, std::fabs(Ax[p]));
+    *bottleneck = b;
+  }
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// Strongly connected components (Tarjan, iterative) of the directed graph with an
+// edge j -> r for every off-diagonal entry B(r, j), B = A with column j's matched row
+// moved to position j.  Components are emitted sinks first, which makes the
+// permuted matrix block upper triangular.  perm: new index -> old column index.
+// ---------------------------------------------------------------------------
+int scc_order(int n, const int32_t* Ap, const int32_t* Ai, const int32_t* row_of_col,
+              std::vector<int32_t>& perm, std::vector<int32_t>& blkptr) {
+  std::vector<int32_t> col_of_row(n);
+  for (int j = 0; j < n; j++) col_of_row[row_of_col[j]] = j;
+  std::vector<int32_t> index(n, -1), low(n, 0), stack, cstack, pos(n), comp(n, -1);
+  std::vector<char> onstack(n, 0);
+  stack.reserve(n);
+  cstack.reserve(n);
+  int counter = 0, ncomp = 0;
+  std::vector<int32_t> order;
+  order.reserve(n);
+  blkptr.assign(1, 0);
+  for (int s = 0; s < n; s++) {
+    if (index[s] >= 0) continue;
+    cstack.push_back(s);
+    index[s] = low[s] = counter++;
+    pos[s] = Ap[s];
+    stack.push_back(s);
+    onstack[s] = 1;
+    while (!cstack.empty()) {
+      int v = cstack.back();
+      bool descended = false;
+      while (pos[v] < Ap[v + 1]) {
+        int w = col_of_row[Ai[pos[v]]];
+        pos[v]++;
+        if (w == v) continue;
+        if (index[w] < 0) {
+          index[w] = low[w] = counter++;
+          pos[w] = Ap[w];
+          stack.push_back(w);
+          onstack[w] = 1;
+          cstack.push_back(w);
+          descended = true;
+          break;
+        } else if (onstack[w]) {
+          low[v] = std::min(low[v], index[w]);
+        }
+      }
+      if (descended) continue;
+      cstack.pop_back();
+      if (!cstack.empty()) low[cstack.back()] = std::min(low[cstack.back()], low[v]);
+      if (low[v] == index[v]) {
+        // pop the component; list its nodes in ascending index for determinism
+        size_t start = order.size();
+        while (true) {
+          int w = stack.back();
+          stack.pop_back();
+          onstack[w] = 0;
+          comp[w] = ncomp;
+          order.push_back(w);
+          if (w == v) break;
+        }
+        std::sort(order.begin() + (long)start, order.end());
+        ncomp++;
+        blkptr.push_back((int32_t)order.size());
+      }
+    }
+  }
+  perm = order;
+  return ncomp;
+}
+
+// ---------------------------------------------------------------------------
+// Minimum-degree ordering on a symmetric graph using a quotient graph of
+// variables and elements with approximate external degrees (the scheme of
+// Amestoy, Davis and Duff's approximate minimum degree; no supervariables).
+// Returns perm: new -> old.
+// ---------------------------------------------------------------------------
+std::vector<int32_t> min_degree_order(int n, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj) {
+  std::vector<int32_t> perm;
+  perm.reserve(n);
+  if (n == 0) return perm;
+  std::vector<std::vector<int32_t>> vadj(n), eadj(n), elem(n);
+  std::vector<int32_t> deg(n), esize(n, 0);
+  std::vector<char> state(n, 0);  // 0 variable, 1 element (alive), 2 dead element
+  for (int i = 0; i < n; i++) {
+    vadj[i].assign(adj.begin() + xadj[i], adj.begin() + xadj[i + 1]);
+    deg[i] = (int32_t)vadj[i].size();
+  }
+  // degree buckets (doubly linked)
+  std::vector<int32_t> head(n + 1, -1), next(n, -1), prev(n, -1);
+  auto insert = [&](int i) {
+    int d = deg[i];
+    next[i] = head[d];
+    prev[i] = -1;
+    if (head[d] >= 0) prev[head[d]] = i;
+    head[d] = i;
+  };
+  auto remove = [&](int i) {
+    int d = deg[i];
+    if (prev[i] >= 0) next[prev[i]] = next[i]; else head[d] = next[i];
+    if (next[i] >= 0) prev[next[i]] = prev[i];
+  };
+  for (int i = n - 1; i >= 0; i--) insert(i);
+  std::vector<int32_t> mark(n, -1), w(n, -1);
+  std::vector<int32_t> Lp;
+  int mindeg = 0;
+  for (int k = 0; k < n; k++) {
+    while (mindeg <= n && head[mindeg] < 0) mindeg++;
+    int p = head[mindeg];
+    remove(p);
+    perm.push_back(p);
+    // Lp = adjacent variables plus the variables of adjacent elements
+    Lp.clear();
+    mark[p] = p;
+    for (int v : vadj[p])
+      if (state[v] == 0 && mark[v] != p) { mark[v] = p; Lp.push_back(v); }
+    for (int e : eadj[p]) {
+      if (state[e] != 1) continue;
+      for (int v : elem[e])
+        if (state[v] == 0 && mark[v] != p) { mark[v] = p; Lp.push_back(v); }
+      state[e] = 2;
+      std::vector<int32_t>().swap(elem[e]);
+    }
+    state[p] = 1;
+    elem[p] = Lp;
+    esize[p] = (int32_t)Lp.size();
+    std::vector<int32_t>().swap(vadj[p]);
+    std::vector<int32_t>().swap(eadj[p]);
+    const int lsz = (int)Lp.size();
+    // |Le \ Lp| for elements adjacent to Lp
+    std::vector<int32_t> touched;
+    for (int i : Lp) {
+      for (int e : eadj[i]) {
+        if (state[e] != 1 || e == p) continue;
+        if (w[e] < 0) { w[e] = esize[e]; touched.push_back(e); }
+        w[e]--;
+      }
+    }
+    const int remaining = n - k - 1;
+    for (int i : Lp) {
+      remove(i);
+      // prune element list, drop elements absorbed by p (Le subset of Lp), add p
+      auto& E = eadj[i];
+      size_t o = 0;
+      int64_t esum = 0;
+      for (int e : E) {
+        if (state[e] != 1 || e == p) continue;
+        if (w[e] == 0) { state[e] = 2; continue; }   // aggressive absorption
+        E[o++] = e;
+        esum += w[e];
+      }
+      E.resize(o);
+      E.push_back(p);
+      // prune variable list: drop variables covered by p's element
+      auto& V = vadj[i];
+      o = 0;
+      for (int v : V)
+        if (state[v] == 0 && mark[v] != p && v != i) V[o++] = v;
+      V.resize(o);
+      int64_t d = (int64_t)V.size() + (lsz - 1) + esum;
+      d = std::min<int64_t>(d, (int64_t)deg[i] + lsz - 1);
+      d = std::min<int64_t>(d, remaining > 0 ? remaining - 1 : 0);
+      if (d < 0) d = 0;
+      deg[i] = (int32_t)d;
+      insert(i);
+      if (d < mindeg) mindeg = (int)d;
+    }
+    for (int e : touched) w[e] = -1;
+  }
+  return perm;
+}
+
+namespace {
+
+// Column elimination tree of B^T B for columns [b0, b1) of the diagonal block part of R
+// (Liu's algorithm with path compression; CSparse's cs_etree, ata variant).
+void block_col_etree(int b0, int b1, const std::vector<int32_t>& Rp, const std::vector<int32_t>& Ri,
+                     std::vector<int32_t>& parent, std::vector<int32_t>& prev, std::vector<int32_t>& anc,
+                     int r0 = -1, int r1 = -1) {
+  if (r0 < 0) { r0 = b0; r1 = b1; }
+  for (int k = r0; k < r1; k++) prev[k] = -1;
+  for (int k = b0; k < b1; k++) {
+    parent[k] = -1;
+    anc[k] = -1;
+    for (int32_t p = Rp[k]; p < Rp[k + 1]; p++) {
+      int32_t i = Ri[p];
+      if (i < r0 || i >= r1) continue;
+      int32_t j = prev[i];
+      while (j != -1 && j < k) {
+        int32_t jn = anc[j];
+        anc[j] = k;
+        if (jn == -1) { parent[j] = k; break; }
+        j = jn;
+      }
+      prev[i] = k;
+    }
+  }
+}
+
+// Symmetric adjacency of B+B^T restricted to the index set `nodes` (given in the
+// global column numbering via pos_of: global -> local, -1 outside).
+void local_graph(const std::vector<int32_t>& nodes, const std::vector<int32_t>& pos_of,
+                 const int32_t* Ap, const int32_t* Ai, const std::vector<int32_t>& row_to_node,
+                 std::vector<int64_t>& xadj, std::vector<int32_t>& adj) {
+  const int m = (int)nodes.size();
+  std::vector<std::vector<int32_t>> nb(m);
+  for (int a = 0; a < m; a++) {
+    int c = nodes[a];
+    for (int32_t p = Ap[c]; p < Ap[c + 1]; p++) {
+      int r = row_to_node[Ai[p]];
+      int b = pos_of[r];
+      if (b < 0 || b == a) continue;
+      nb[a].push_back(b);
+      nb[b].push_back(a);
+    }
+  }
+  xadj.assign(m + 1, 0);
+  adj.clear();
+  for (int a = 0; a < m; a++) {
+    auto& v = nb[a];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    adj.insert(adj.end(), v.begin(), v.end());
+    xadj[a + 1] = (int64_t)adj.size();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Nested dissection of one block (Sec. III-C) by recursive vertex bisection.
+// Each bisection: breadth-first level structure from a pseudo-peripheral vertex
+// (George and Liu), the smallest level near the middle as the separator, then a
+// pass that moves separator vertices touching only one side into that side.
+// Disconnected parts are split by whole components with an empty separator.
+// ---------------------------------------------------------------------------
+struct NdBuild {
+  const std::vector<int64_t>& xadj;
+  const std::vector<int32_t>& adj;
+  std::vector<int32_t> part;    // current subset id per local vertex
+  std::vector<int32_t> level;
+  std::vector<int32_t> queue;
+  int next_id = 1;
+};
+
+// BFS inside subset `id` from `src`; returns the last vertex reached and fills level
+static int bfs_levels(NdBuild& B, int id, int src, const std::vector<int32_t>& verts, int* nlev) {
+  for (int v : verts) B.level[v] = -1;
+  B.queue.clear();
+  B.queue.push_back(src);
+  B.level[src] = 0;
+  size_t h = 0;
+  int last = src;
+  while (h < B.queue.size()) {
+    int v = B.queue[h++];
+    last = v;
+    for (int64_t p = B.xadj[v]; p < B.xadj[v + 1]; p++) {
+      int w = B.adj[p];
+      if (B.part[w] == id && B.level[w] < 0) { B.level[w] = B.level[v] + 1; B.queue.push_back(w); }
+    }
+  }
+  *nlev = B.level[last] + 1;
+  return last;
+}
+
+// split `verts` (subset id) into (left, right, sep)
+static void bisect(NdBuild& B, int id, const std::vector<int32_t>& verts, std::vector<int32_t>& left,
+                   std::vector<int32_t>& right, std::vector<int32_t>& sep) {
+  left.clear(); right.clear(); sep.clear();
+  const int m = (int)verts.size();
+  if (m == 0) return;
+  int nlev = 0;
+  int far = bfs_levels(B, id, verts[0], verts, &nlev);
+  if ((int)B.queue.size() < m) {
+    // disconnected: whole components to the two sides, smaller ones first to the lighter
+    std::vector<std::vector<int32_t>> comps;
+    std::vector<char> seen(0);
+    for (int v : verts) B.level[v] = -1;
+    for (int v : verts) {
+      if (B.level[v] >= 0) continue;
+      int dummy;
+      (void)dummy;
+      B.queue.clear();
+      B.queue.push_back(v);
+      B.level[v] = 0;
+      size_t h = 0;
+      while (h < B.queue.size()) {
+        int x = B.queue[h++];
+        for (int64_t p = B.xadj[x]; p < B.xadj[x + 1]; p++) {
+          int w = B.adj[p];
+          if (B.part[w] == id && B.level[w] < 0) { B.level[w] = 0; B.queue.push_back(w); }
+        }
+      }
+      comps.push_back(B.queue);
+    }
+    std::stable_sort(comps.begin(), comps.end(),
+                     [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) { return a.size() > b.size(); });
+    for (auto& c : comps) {
+      auto& dst = left.size() <= right.size() ? left : right;
+      dst.insert(dst.end(), c.begin(), c.end());
+    }
+    return;
+  }
+  // pseudo-peripheral vertex: repeat BFS from the farthest vertex while the depth grows
+  int src = far;
+  for (int it = 0; it < 4; it++) {
+    int nl2 = 0;
+    int f2 = bfs_levels(B, id, src, verts, &nl2);
+    if (nl2 <= nlev) break;
+    nlev = nl2;
+    src = f2;
+  }
+  int nl = 0;
+  bfs_levels(B, id, src, verts, &nl);
+  if (nl < 3) {
+    // too shallow to cut by levels: take everything after the first level as the separator
+    for (int v : verts) (B.level[v] == 0 ? left : sep).push_back(v);
+    return;
+  }
+  std::vector<int64_t> cnt(nl, 0);
+  for (int v : verts) cnt[B.level[v]]++;
+  // smallest level whose cumulative count before it lies in [35%, 65%] of m
+  int64_t acc = 0;
+  int best = -1;
+  int64_t bestsz = INT64_MAX;
+  for (int l = 0; l < nl; l++) {
+    if (l > 0 && l < nl - 1 && acc >= (int64_t)(0.35 * m) && acc <= (int64_t)(0.65 * m) && cnt[l] < bestsz) {
+      bestsz = cnt[l];
+      best = l;
+    }
+    acc += cnt[l];
+  }
+  if (best < 0) {
+    acc = 0;
+    for (int l = 0; l < nl; l++) {
+      if (acc + cnt[l] > m / 2 || l == nl - 2) { best = std::max(1, std::min(l, nl - 2)); break; }
+      acc += cnt[l];
+    }
+  }
+  for (int v : verts) {
+    int l = B.level[v];
+    (l < best ? left : (l > best ? right : sep)).push_back(v);
+  }
+  // separator cleanup: a separator vertex without neighbours on one side joins the other
+  const int idL = B.next_id++, idR = B.next_id++, idS = B.next_id++;
+  for (int v : left) B.part[v] = idL;
+  for (int v : right) B.part[v] = idR;
+  for (int v : sep) B.part[v] = idS;
+  std::vector<int32_t> keep;
+  for (int v : sep) {
+    bool hasL = false, hasR = false;
+    for (int64_t p = B.xadj[v]; p < B.xadj[v + 1]; p++) {
+      int w = B.adj[p];
+      if (B.part[w] == idL) hasL = true;
+      else if (B.part[w] == idR) hasR = true;
+    }
+    if (!hasR) { B.part[v] = idL; left.push_back(v); }
+    else if (!hasL) { B.part[v] = idR; right.push_back(v); }
+    else keep.push_back(v);
+  }
+  sep.swap(keep);
+  for (int v : left) B.part[v] = id;
+  for (int v : right) B.part[v] = id;
+  for (int v : sep) B.part[v] = id;
+}
+
+// Recursive ND: appends the tree nodes in postorder (left, right, separator) and the
+// vertex order.  Returns the node index of this subtree's root.
+static int nd_recurse(NdBuild& B, std::vector<int32_t>& verts, int depth, int max_depth,
+                      std::vector<std::vector<int32_t>>& node_verts, std::vector<int32_t>& node_parent,
+                      std::vector<int32_t>& node_level, std::vector<char>& node_leaf) {
+  if (depth == max_depth || verts.size() < 4) {
+    int idx = (int)node_verts.size();
+    node_verts.push_back(verts);
+    node_parent.push_back(-1);
+    node_level.push_back(0);
+    node_leaf.push_back(1);
+    return idx;
+  }
+  const int id = B.part[verts[0]];
+  std::vector<int32_t> left, right, sep;
+  bisect(B, id, verts, left, right, sep);
+  const int idL = B.next_id++, idR = B.next_id++;
+  for (int v : left) B.part[v] = idL;
+  for (int v : right) B.part[v] = idR;
+  for (int v : sep) B.part[v] = -1;
+  int cl = nd_recurse(B, left, depth + 1, max_depth, node_verts, node_parent, node_level, node_leaf);
+  int cr = nd_recurse(B, right, depth + 1, max_depth, node_verts, node_parent, node_level, node_leaf);
+  int idx = (int)node_verts.size();
+  node_verts.push_back(sep);
+  node_parent.push_back(-1);
+  node_level.push_back(std::max(node_level[cl], node_level[cr]) + 1);
+  node_leaf.push_back(0);
+  node_parent[cl] = idx;
+  node_parent[cr] = idx;
+  return idx;
+}
+
+// R's diagonal-block and off-diagonal-block parts from the final permutations.
+int assemble_R(int n, const int32_t* Ap, const int32_t* Ai, Plan& P) {
+  std::vector<int32_t> blk(n);
+  for (size_t b = 0; b + 1 < P.blkptr.size(); b++)
+    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk[k] = (int32_t)b;
+  P.Rp.assign(n + 1, 0);
+  P.Op.assign(n + 1, 0);
+  P.Ri.clear(); P.Rmap.clear(); P.Oi.clear(); P.Omap.clear();
+  std::vector<std::pair<int32_t, int32_t>> tmp;
+  for (int k = 0; k < n; k++) {
+    int c = P.qcol[k];
+    tmp.clear();
+    for (int32_t p = Ap[c]; p < Ap[c + 1]; p++) tmp.push_back({P.pinvrow[Ai[p]], p});
+    std::sort(tmp.begin(), tmp.end());
+    for (auto& t : tmp) {
+      int i = t.first;
+      if (blk[i] == blk[k]) { P.Ri.push_back(i); P.Rmap.push_back(t.second); }
+      else if (blk[i] < blk[k]) { P.Oi.push_back(i); P.Omap.push_back(t.second); }
+      else { P.error = "entry below the diagonal blocks (not block upper triangular)"; return -1; }
+    }
+    P.Rp[k + 1] = (int32_t)P.Ri.size();
+    P.Op[k + 1] = (int32_t)P.Oi.size();
+  }
+  return 0;
+}
+
+// Dependency forest, depths and the initial ready list (deepest first).
+void finish_schedule(Plan& P) {
+  const int n = P.n;
+  P.nchild.assign(n, 0);
+  P.depth.assign(n, 0);
+  for (int k = 0; k < n; k++)
+    if (P.parent[k] >= 0) P.nchild[P.parent[k]]++;
+  int md = 0;
+  for (int k = n - 1; k >= 0; k--) {
+    P.depth[k] = P.parent[k] < 0 ? 0 : P.depth[P.parent[k]] + 1;
+    md = std::max(md, P.depth[k]);
+  }
+  P.max_depth = md;
+  P.ready.clear();
+  for (int k = 0; k < n; k++)
+    if (P.nchild[k] == 0) P.ready.push_back(k);
+  std::stable_sort(P.ready.begin(), P.ready.end(),
+                   [&](int a, int b) { return P.depth[a] > P.depth[b]; });
+  P.col_grp.assign(n, 0);
+  for (size_t g = 0; g + 1 < P.grpptr.size(); g++)
+    for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) P.col_grp[k] = (int32_t)g;
+}
+
+}  // namespace
+
+int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
+               const SymbolicOptions& opt, Plan& P) {
+  P = Plan();
+  P.n = n;
+  if (!validate_csc(n, Ap, Ai, P.error)) return -1;
+  P.nnz = Ap[n];
+  // 1. matching: row_of_col[j] = row of A placed on the diagonal at column j
+  std::vector<int32_t> row_of_col;
+  if (opt.matching) {
+    P.struct_rank = bottleneck_matching(n, Ap, Ai, Ax, row_of_col, &P.bottleneck);
+  } else {
+    row_of_col.assign(n, -1);
+    P.struct_rank = max_matching(n, Ap, Ai, nullptr, 0.0, row_of_col);
+  }
+  if (P.struct_rank < n) { P.error = "structurally singular"; return -2; }
+  // 2. BTF: strongly connected components
+  std::vector<int32_t> perm0, blk0;
+  if (opt.btf) {
+    scc_order(n, Ap, Ai, row_of_col.data(), perm0, blk0);
+  } else {
+    perm0.resize(n);
+    std::iota(perm0.begin(), perm0.end(), 0);
+    blk0 = {0, n};
+  }
+  // 3. order every block; node space = column index c of A (row partner row_of_col[c])
+  std::vector<int32_t> row_to_node(n);
+  for (int c = 0; c < n; c++) row_to_node[row_of_col[c]] = c;
+  std::vector<int32_t> pos_of(n, -1);
+  std::vector<int32_t> final_perm;
+  final_perm.reserve(n);
+  P.blkptr.assign(1, 0);
+  P.grpptr.assign(1, 0);
+  std::vector<int64_t> xadj;
+  std::vector<int32_t> adj;
+  struct NdBlockInfo { int b; std::vector<int32_t> node_size, node_parent; std::vector<char> node_leaf; };
+  std::vector<NdBlockInfo> ndinfo;
+  for (size_t b = 0; b + 1 < blk0.size(); b++) {
+    int s0 = blk0[b], s1 = blk0[b + 1], sz = s1 - s0;
+    std::vector<int32_t> nodes(perm0.begin() + s0, perm0.begin() + s1);
+    if (opt.nd_leaves > 1 && sz >= opt.nd_min_block) {
+      // nested dissection with opt.nd_leaves leaves; every tree node becomes a group
+      for (int a = 0; a < sz; a++) pos_of[nodes[a]] = a;
+      local_graph(nodes, pos_of, Ap, Ai, row_to_node, xadj, adj);
+      for (int a = 0; a < sz; a++) pos_of[nodes[a]] = -1;
+      NdBuild B{xadj, adj, std::vector<int32_t>(sz, 0), std::vector<int32_t>(sz, -1), {}, 1};
+      std::vector<int32_t> all(sz);
+      std::iota(all.begin(), all.end(), 0);
+      int levels = 0;
+      while ((1 << levels) < opt.nd_leaves) levels++;
+      std::vector<std::vector<int32_t>> nv;
+      std::vector<int32_t> npar, nlev;
+      std::vector<char> nleaf;
+      nd_recurse(B, all, 0, levels, nv, npar, nlev, nleaf);
+      NdBlockInfo info;
+      info.b = (int)P.blkptr.size() - 1;
+      std::vector<int32_t> sub_pos(sz, -1);
+      for (size_t t = 0; t < nv.size(); t++) {
+        auto& vs = nv[t];
+        std::vector<int32_t> order_local = vs;
+        if (opt.fill_order && vs.size() > 2) {
+          // minimum degree on the node's induced subgraph
+          std::vector<int32_t> gnodes(vs.size());
+          for (size_t a = 0; a < vs.size(); a++) { gnodes[a] = nodes[vs[a]]; pos_of[gnodes[a]] = (int32_t)a; }
+          std::vector<int64_t> sx;
+          std::vector<int32_t> sa;
+          local_graph(gnodes, pos_of, Ap, Ai, row_to_node, sx, sa);
+          for (size_t a = 0; a < vs.size(); a++) pos_of[gnodes[a]] = -1;
+          std::vector<int32_t> lp = min_degree_order((int)vs.size(), sx, sa);
+          for (size_t a = 0; a < vs.size(); a++) order_local[a] = vs[lp[a]];
+        }
+        for (int v : order_local) final_perm.push_back(nodes[v]);
+        if (!vs.empty()) P.grpptr.push_back((int32_t)final_perm.size());
+        info.node_size.push_back((int32_t)vs.size());
+        info.node_parent.push_back(npar[t]);
+        info.node_leaf.push_back(nleaf[t]);
+      }
+      ndinfo.push_back(std::move(info));
+      P.n_nd_blocks++;
+      P.blkptr.push_back((int32_t)final_perm.size());
+      continue;
+    }
+    if (opt.fill_order && sz > 2) {
+      for (int a = 0; a < sz; a++) pos_of[nodes[a]] = a;
+      local_graph(nodes, pos_of, Ap, Ai, row_to_node, xadj, adj);
+      std::vector<int32_t> lp = min_degree_order(sz, xadj, adj);
+      for (int a = 0; a < sz; a++) pos_of[nodes[a]] = -1;
+      for (int a = 0; a < sz; a++) final_perm.push_back(nodes[lp[a]]);
+    } else {
+      final_perm.insert(final_perm.end(), nodes.begin(), nodes.end());
+    }
+    P.blkptr.push_back((int32_t)final_perm.size());
+    P.grpptr.push_back((int32_t)final_perm.size());
+  }
+  // 4. compose: R(k, l) = A(row_of_col[perm[k]], perm[l])
+  P.prow.resize(n);
+  P.qcol.resize(n);
+  P.pinvrow.resize(n);
+  for (int k = 0; k < n; k++) {
+    P.qcol[k] = final_perm[k];
+    P.prow[k] = row_of_col[final_perm[k]];
+  }
+  for (int k = 0; k < n; k++) P.pinvrow[P.prow[k]] = k;
+  if (assemble_R(n, Ap, Ai, P) != 0) return -1;
+  // 5. schedule.  Plain blocks: the column elimination tree of the block (George and
+  // Ng: it bounds the dependencies of partial pivoting for any pivot sequence).  ND
+  // blocks: pivots stay inside each node, so a leaf depends only on itself (the
+  // column elimination tree of its own rows and columns), a separator's columns form
+  // a chain, and every node's exit columns feed the first column of its nearest
+  // non-empty ancestor.
+  P.parent.assign(n, -1);
+  std::vector<int32_t> prev(n), anc(n);
+  std::vector<char> is_nd(P.blkptr.size(), 0);
+  for (auto& info : ndinfo) is_nd[info.b] = 1;
+  for (size_t b = 0; b + 1 < P.blkptr.size(); b++)
+    if (!is_nd[b]) block_col_etree(P.blkptr[b], P.blkptr[b + 1], P.Rp, P.Ri, P.parent, prev, anc);
+  for (auto& info : ndinfo) {
+    const int nn = (int)info.node_size.size();
+    std::vector<int32_t> c0(nn), c1(nn);
+    int c = P.blkptr[info.b];
+    for (int t = 0; t < nn; t++) { c0[t] = c; c += info.node_size[t]; c1[t] = c; }
+    auto target_of = [&](int t) {
+      int u = info.node_parent[t];
+      while (u >= 0 && info.node_size[u] == 0) u = info.node_parent[u];
+      return u < 0 ? -1 : c0[u];
+    };
+    for (int t = 0; t < nn; t++) {
+      if (info.node_size[t] == 0) continue;
+      const int tgt = target_of(t);
+      if (info.node_leaf[t]) {
+        block_col_etree(c0[t], c1[t], P.Rp, P.Ri, P.parent, prev, anc, c0[t], c1[t]);
+        for (int k = c0[t]; k < c1[t]; k++)
+          if (P.parent[k] < 0) P.parent[k] = tgt;
+      } else {
+        for (int k = c0[t]; k + 1 < c1[t]; k++) P.parent[k] = k + 1;
+        P.parent[c1[t] - 1] = tgt;
+      }
+      NdNode nd;
+      nd.g0 = c0[t]; nd.g1 = c1[t]; nd.parent = info.node_parent[t]; nd.level = 0; nd.leaf = info.node_leaf[t];
+      P.nd_nodes.push_back(nd);
+    }
+  }
+  finish_schedule(P);
+  // ND tree over groups
+  P.grp_parent.assign(P.grpptr.size() - 1, -1);
+  for (auto& info : ndinfo) {
+    const int nn = (int)info.node_size.size();
+    std::vector<int32_t> c0(nn);
+    int c = P.blkptr[info.b];
+    for (int t = 0; t < nn; t++) { c0[t] = c; c += info.node_size[t]; }
+    auto group_at = [&](int col) {
+      return (int32_t)(std::upper_bound(P.grpptr.begin(), P.grpptr.end(), col) - P.grpptr.begin() - 1);
+    };
+    for (int t = 0; t < nn; t++) {
+      if (info.node_size[t] == 0) continue;
+      int u = info.node_parent[t];
+      while (u >= 0 && info.node_size[u] == 0) u = info.node_parent[u];
+      if (u >= 0) P.grp_parent[group_at(c0[t])] = group_at(c0[u]);
+    }
+  }
+  return 0;
+}
+
+int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
+                    const int32_t* prow, const int32_t* qcol,
+                    int nblk, const int32_t* blkptr, int ngrp, const int32_t* grpptr, Plan& P) {
+  P = Plan();
+  P.n = n;
+  if (!validate_csc(n, Ap, Ai, P.error)) return -1;
+  P.nnz = Ap[n];
+  P.prow.assign(prow, prow + n);
+  P.qcol.assign(qcol, qcol + n);
+  P.pinvrow.assign(n, -1);
+  std::vector<char> seen(n, 0);
+  for (int k = 0; k < n; k++) {
+    if (prow[k] < 0 || prow[k] >= n || P.pinvrow[prow[k]] >= 0) { P.error = "prow not a permutation"; return -1; }
+    P.pinvrow[prow[k]] = k;
+    if (qcol[k] < 0 || qcol[k] >= n || seen[qcol[k]]) { P.error = "qcol not a permutation"; return -1; }
+    seen[qcol[k]] = 1;
+  }
+  if (nblk < 1 || ngrp < 1 || blkptr[0] != 0 || blkptr[nblk] != n || grpptr[0] != 0 || grpptr[ngrp] != n) {
+    P.error = "bad block/group pointers";
+    return -1;
+  }
+  P.blkptr.assign(blkptr, blkptr + nblk + 1);
+  P.grpptr.assign(grpptr, grpptr + ngrp + 1);
+  for (int b = 0; b < nblk; b++)
+    if (blkptr[b + 1] <= blkptr[b]) { P.error = "empty block"; return -1; }
+  {
+    int b = 0;
+    for (int g = 0; g < ngrp; g++) {
+      if (grpptr[g + 1] <= grpptr[g]) { P.error = "empty group"; return -1; }
+      while (blkptr[b + 1] <= grpptr[g]) b++;
+      if (grpptr[g + 1] > blkptr[b + 1]) { P.error = "group crosses a block boundary"; return -1; }
+    }
+  }
+  P.struct_rank = n;
+  if (assemble_R(n, Ap, Ai, P) != 0) return -1;
+  P.parent.assign(n, -1);
+  std::vector<int32_t> prev(n), anc(n);
+  for (int b = 0; b < nblk; b++) block_col_etree(P.blkptr[b], P.blkptr[b + 1], P.Rp, P.Ri, P.parent, prev, anc);
+  finish_schedule(P);
+  P.grp_parent.assign(P.grpptr.size() - 1, -1);
+  return 0;
+}
+
+}  // namespace basker

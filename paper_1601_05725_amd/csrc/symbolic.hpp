@@ -1,0 +1,78 @@
+// Host-side symbolic analysis: orderings and the static plan the GPU kernels run.
+//
+// Builds R = A(prow, qcol) in block upper triangular form (Sec. III-A: a bottleneck
+// matching puts large entries on the diagonal, then strongly connected components
+// give the diagonal blocks), orders every small block for fill (Alg. 2, line 2) and
+// the large blocks by nested dissection with a fill order inside every node
+// (Sec. III-C), and derives the candidate groups (pivots stay inside a BTF block or
+// an ND node) and the column dependency forest the numeric kernels schedule on.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace basker {
+
+struct SymbolicOptions {
+  int matching = 1;        // bottleneck matching (else: structural matching only)
+  int btf = 1;             // split into strongly connected components
+  int fill_order = 1;      // minimum-degree order inside blocks / ND nodes
+  int nd_leaves = 16;      // leaves of the ND tree (power of two)
+  int nd_min_block = 10000;// blocks at least this large are ordered by ND
+};
+
+struct NdNode {            // one node of the ND tree of a large block (postorder)
+  int g0, g1;              // columns (= rows) in R
+  int parent;              // index into nodes, -1 at the root
+  int level;               // 0 at leaves
+  bool leaf;
+};
+
+struct Plan {
+  int n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> prow, qcol, pinvrow;   // R(i,k) = A(prow[i], qcol[k]); pinvrow = inverse of prow
+  std::vector<int32_t> blkptr;                // BTF blocks
+  std::vector<int32_t> grpptr;                // candidate groups (contiguous, nested in blocks)
+  std::vector<int32_t> col_grp;               // group of each column
+  std::vector<int32_t> grp_parent;            // ND tree over groups (-1: root or not ND)
+  // diagonal-block part of R (factored), rows ascending; map = position in A's value array
+  std::vector<int32_t> Rp, Ri, Rmap;
+  // strictly upper off-diagonal-block part of R (solve only)
+  std::vector<int32_t> Op, Oi, Omap;
+  // column dependency forest: parent[k] > k or -1, nchild[k]; initial ready columns by priority
+  std::vector<int32_t> parent, nchild, ready;
+  std::vector<int32_t> depth;
+  std::vector<NdNode> nd_nodes;
+  int struct_rank = 0;
+  double bottleneck = 0.0;
+  int max_depth = 0;
+  int n_nd_blocks = 0;
+  std::string error;
+};
+
+// Full pipeline from a CSC matrix (values used by the matching).  Returns 0, or a
+// negative status (-1 invalid input, -2 structurally singular).
+int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
+               const SymbolicOptions& opt, Plan& plan);
+
+// Plan from a caller-supplied ordering: R = A(prow, qcol), BTF blocks blkptr[0..nblk],
+// candidate groups grpptr[0..ngrp] nested in the blocks.  Lower off-diagonal blocks
+// must be empty.  The schedule is the column elimination tree of each block, which
+// is safe for any pivot sequence.
+int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
+                    const int32_t* prow, const int32_t* qcol,
+                    int nblk, const int32_t* blkptr, int ngrp, const int32_t* grpptr,
+                    Plan& plan);
+
+// exposed for tests of the orderings
+int max_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax, double thresh,
+                 std::vector<int32_t>& match_row_of_col);
+int bottleneck_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
+                        std::vector<int32_t>& match_row_of_col, double* bottleneck);
+int scc_order(int n, const int32_t* Ap, const int32_t* Ai, const int32_t* row_of_col,
+              std::vector<int32_t>& perm, std::vector<int32_t>& blkptr);
+std::vector<int32_t> min_degree_order(int n, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj);
+
+}  // namespace basker

@@ -169,8 +169,9 @@ def mna_triplets(n: int, key: int, p_long: float = 1e-3, edges_per_node: int = 3
     1 + Geom(0.25), or with probability p_long at a uniform node.  Conductances are
     log-uniform in [g_lo, g_hi] and stamped symmetrically.  Node 0 and 1% of nodes are
     grounded.  Auxiliary nodes hang off a random graph node and are grounded.  There
-    are n_aux controlled-source entries U(-1,1) at random off-diagonal node positions,
-    and n_vs voltage sources, each tying a distinct graph node to ground through a
+    are n_aux controlled-source entries U(-1,1) at random off-diagonal node positions
+    (uniform for n <= 2,000; above that at a local offset, uniform only with
+    probability p_long, so large circuits keep circuit-like fill), and n_vs voltage sources, each tying a distinct graph node to ground through a
     +1/+1 pair with no diagonal entry.
     """
     n_g, n_aux, n_vs = mna_parts(n)
@@ -217,10 +218,17 @@ def mna_triplets(n: int, key: int, p_long: float = 1e-3, edges_per_node: int = 3
         R.append(np.concatenate([a, tgt, a, tgt])); C.append(np.concatenate([a, tgt, tgt, a]))
         V.append(np.concatenate([g, g, -g, -g]))
         R.append(a); C.append(a); V.append(s.log_uniform(g_lo, g_hi, n_aux))
-        # controlled sources: off-diagonal node positions
+        # controlled sources: off-diagonal node positions -- uniform up to n = 2,000;
+        # above that local like the resistor partners (uniform with probability p_long)
         nn = n_g + n_aux
         i = s.integers(0, nn, n_aux)
         j = (i + 1 + s.integers(0, nn - 1, n_aux)) % nn
+        if n > 2000:
+            off = 1 + s.geometric(0.25, n_aux)
+            sign = np.where(s.uniform(n_aux) < 0.5, -1, 1)
+            jl = np.clip(i + sign * off, 0, nn - 1)
+            jl = np.where(jl == i, np.where(i > 0, i - 1, i + 1), jl)
+            j = np.where(s.uniform(n_aux) < p_long, j, jl)
         R.append(i); C.append(j); V.append(2.0 * s.uniform(n_aux) - 1.0)
     # voltage sources
     if n_vs > 0:
@@ -234,10 +242,18 @@ def mna_triplets(n: int, key: int, p_long: float = 1e-3, edges_per_node: int = 3
     return rows, cols, vals
 
 
-def gen_mna(n: int, seed: int = BASE_SEED, relabel: bool = True, p_long: float = 1e-3) -> Csc:
-    """One irreducible, nonsingular MNA circuit matrix of order n (about 6.6 nnz/row)."""
+def mna_p_long(n: int) -> float:
+    """Probability of a uniform long-range partner: 1e-3 up to n = 2,000, then
+    1e-3 * sqrt(2000 / n), so the number of long branches grows like sqrt(n) (a
+    Rent-exponent-1/2 circuit) instead of linearly, which would make large circuits
+    expanders with fill far above the circuit range (|L+U|/|A| < 4)."""
+    return 1e-3 if n <= 2000 else 1e-3 * np.sqrt(2000.0 / n)
+
+
+def gen_mna(n: int, seed: int = BASE_SEED, relabel: bool = True, p_long: float | None = None) -> Csc:
+    """One nonsingular MNA circuit matrix of order n (about 6 nnz/row)."""
     key = substream_key(seed, 0x4D4E41)
-    r, c, v = mna_triplets(n, key, p_long=p_long)
+    r, c, v = mna_triplets(n, key, p_long=mna_p_long(n) if p_long is None else p_long)
     a = csc_from_coo(n, r, c, v)
     if relabel:
         a = symmetric_relabel(a, Stream(substream_key(seed, 0x5045524D)).permutation(n))
@@ -323,7 +339,7 @@ def gen_batched_btf(nblocks: int = 50000, big: int = 100000, seed: int = BASE_SE
     n = int(off[-1])
     R, C, V = [], [], []
     for b, s_b in enumerate(all_sizes):
-        r, c, v = mna_triplets(int(s_b), substream_key(seed, 0x10000000 + b))
+        r, c, v = mna_triplets(int(s_b), substream_key(seed, 0x10000000 + b), p_long=mna_p_long(int(s_b)))
         R.append(r + off[b]); C.append(c + off[b]); V.append(v)
     # upper block-triangular coupling: row i in block b -> columns in blocks > b
     s = Stream(substream_key(seed, 0x434F5550))

@@ -1,0 +1,259 @@
+"""GPU parity: the HIP factorization, refactorization and solve (called through the
+C ABI) against the oracle on the same inputs and orderings.
+
+The kernel updates every column in ascending pivot order with separately rounded
+multiply-subtract and IEEE division, so against the oracle run in that order
+(update_order = ascending) pivots, patterns and values must agree bit for bit.
+Against the oracle's default DFS order the pivots agree at every column whose
+decision margin is not ambiguous (>= 1e-10) and values agree to 1e-12 relative per
+column.  Backward error <= 1e-13 and solve residual <= 1e-12 are checked too.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-12
+BERR_TOL = 1e-13
+RES_TOL = 1e-12
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1601_05725_amd as bk
+    bk.load()
+    return bk
+
+
+@pytest.fixture(scope="module")
+def orc(oracle_lib):
+    return oracle_lib
+
+
+def compare_exact(ext, f):
+    np.testing.assert_array_equal(ext.piv, f.piv)
+    np.testing.assert_array_equal(ext.Lp, f.Lp)
+    np.testing.assert_array_equal(ext.Li, f.Li)
+    np.testing.assert_array_equal(ext.Up, f.Up)
+    np.testing.assert_array_equal(ext.Ui, f.Ui)
+    np.testing.assert_array_equal(ext.Lx, f.Lx)
+    np.testing.assert_array_equal(ext.Ux, f.Ux)
+
+
+def col_rel_err(p, x, y):
+    worst = 0.0
+    for k in range(len(p) - 1):
+        a, b = x[p[k]:p[k + 1]], y[p[k]:p[k + 1]]
+        if a.size:
+            den = max(np.abs(b).max(), 1e-300)
+            worst = max(worst, np.abs(a - b).max() / den)
+    return worst
+
+
+def compare_tol(ext, f):
+    amb = f.margin < 1e-10
+    same = np.array_equal(ext.piv, f.piv)
+    if not same:
+        diff = np.nonzero(ext.piv != f.piv)[0]
+        assert amb[diff[0]], "pivot differs at a non-ambiguous column %d" % diff[0]
+        return False
+    np.testing.assert_array_equal(ext.Lp, f.Lp)
+    np.testing.assert_array_equal(ext.Li, f.Li)
+    np.testing.assert_array_equal(ext.Up, f.Up)
+    np.testing.assert_array_equal(ext.Ui, f.Ui)
+    assert col_rel_err(ext.Lp, ext.Lx, f.Lx) <= VAL_TOL
+    assert col_rel_err(ext.Up, ext.Ux, f.Ux) <= VAL_TOL
+    return True
+
+
+def as_factors(orc, ext, n):
+    return orc.Factors(n, 0, -1, ext.Lp, ext.Li, ext.Lx, ext.Up, ext.Ui, ext.Ux, ext.piv, np.zeros(n), 0.0)
+
+
+def run_case(bk, orc, a, order=None, tau=1e-3, diag_pref=1, label="", nrhs=2, **opt):
+    say("case %s n=%d nnz=%d tau=%g" % (label, a.n, a.nnz, tau))
+    o = bk.default_options(pivot_tol=tau, diag_pref=diag_pref, **opt)
+    if order is None:
+        h = bk.Handle.symbolic(a, o)
+        prow, qcol, bp, gp = h.ordering()
+        order = orc.Ordering(prow, qcol, bp, gp)
+    else:
+        h = bk.Handle.symbolic_ordered(a, order.prow, order.qcol, order.blkptr, order.grpptr, o)
+    h.factor(a.values)
+    ext = h.extract()
+    f_asc = orc.factor(a, order, tau=tau, diag_pref=bool(diag_pref), update_order=orc.ORDER_ASCENDING)
+    assert f_asc.status == 0
+    compare_exact(ext, f_asc)
+    f_dfs = orc.factor(a, order, tau=tau, diag_pref=bool(diag_pref), update_order=orc.ORDER_DFS)
+    compare_tol(ext, f_dfs)
+    berr = orc.backward_error(a, order, as_factors(orc, ext, a.n))
+    assert berr <= BERR_TOL, berr
+    b = synth.rhs(a.n, nrhs)
+    x = h.solve(b)
+    assert orc.residual(a, x, b) <= RES_TOL
+    xo = orc.solve(a, order, f_asc, b)
+    scale = np.abs(xo).max()
+    assert np.abs(x - xo).max() <= 1e-9 * max(scale, 1.0)
+    return h, order, ext
+
+
+# ---------------------------------------------------------------------------
+
+def test_tiny_identity_ordering(bk, orc):
+    a = synth.csc_from_dense(np.array([[1.0, 0, 4], [4, 2, 0], [0, 3, 1]]))
+    run_case(bk, orc, a, orc.Ordering.natural(3), tau=0.1, label="golden3x3")
+    run_case(bk, orc, a, orc.Ordering.natural(3), tau=1.0, diag_pref=0, label="golden3x3-pp")
+
+
+def test_one_by_one_and_diagonal(bk, orc):
+    run_case(bk, orc, synth.csc_from_dense(np.array([[2.5]])), orc.Ordering.natural(1), label="1x1")
+    d = synth.csc_from_dense(np.diag([3.0, -2.0, 0.5, 7.0]))
+    run_case(bk, orc, d, orc.Ordering.natural(4), label="diag")
+
+
+@pytest.mark.parametrize("tau,dp", [(1.0, 0), (0.1, 1), (1e-3, 1)])
+def test_mna_natural_order_forces_pivoting(bk, orc, tau, dp):
+    a = synth.gen_mna(300, seed=21)
+    run_case(bk, orc, a, orc.Ordering.natural(a.n), tau=tau, diag_pref=dp, label="mna300-natural")
+
+
+@pytest.mark.parametrize("n", [64, 300])
+def test_dense(bk, orc, n):
+    """Dense columns: 300 rows exceed the LDS workspace and use the global fallback."""
+    A = synth.random_dense(n, 31 + n)
+    a = synth.csc_from_dense(A)
+    run_case(bk, orc, a, orc.Ordering.natural(n), tau=1.0, diag_pref=0, label="dense%d" % n)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_blocks_and_groups_user_ordering(bk, orc, seed):
+    n = 240
+    a0 = synth.random_sparse(n, 0.03, seed)
+    s = synth.Stream(synth.substream_key(seed, 77))
+    blkptr = np.unique(np.concatenate([[0, n], s.integers(1, n, 12)])).astype(np.int32)
+    grpptr = np.unique(np.concatenate([blkptr, s.integers(1, n, 30)])).astype(np.int32)
+    blk = np.repeat(np.arange(len(blkptr) - 1), np.diff(blkptr))
+    D = a0.to_dense()
+    D = np.where(blk[:, None] > blk[None, :], 0.0, D)
+    pr, pc = s.permutation(n), s.permutation(n)
+    A = np.zeros((n, n))
+    A[np.ix_(pr, pc)] = D
+    a = synth.csc_from_dense(A)
+    order = orc.Ordering(pr.astype(np.int32), pc.astype(np.int32), blkptr, grpptr)
+    run_case(bk, orc, a, order, tau=0.1, label="groups-%d" % seed, nrhs=3)
+
+
+def test_c0_full_pipeline(bk, orc):
+    a = synth.gen_mna(2000)
+    h, order, ext = run_case(bk, orc, a, label="C0", nrhs=1)
+    inf = h.info()
+    say("C0 info %s" % {k: inf[k] for k in ("nblocks", "lnz", "unz", "max_depth", "factor_kernel_ms", "offdiag_pivots")})
+
+
+def test_nd_block(bk, orc):
+    a = synth.gen_mna(12000, seed=6)
+    h, order, ext = run_case(bk, orc, a, label="mna12k-nd", nd_min_block=3000, nd_leaves=8)
+    assert h.info()["nd_blocks"] >= 1
+
+
+def test_batched_btf_small(bk, orc):
+    inp = synth.gen_batched_btf(nblocks=400, big=4000, seed=5)
+    h, order, ext = run_case(bk, orc, inp.a, label="btf400", nd_min_block=2000, nd_leaves=4)
+    assert h.info()["nblocks"] >= 400
+
+
+def test_refactor_bitwise_and_sequence(bk, orc):
+    a = synth.gen_mna(1500, seed=9)
+    h = bk.Handle.symbolic(a)
+    prow, qcol, bp, gp = h.ordering()
+    order = orc.Ordering(prow, qcol, bp, gp)
+    h.factor(a.values)
+    e0 = h.extract()
+    say("refactor same values")
+    assert h.refactor(a.values) == bk.OK
+    compare_exact(h.extract(), orc.factor(a, order, update_order=orc.ORDER_ASCENDING))
+    compare_exact(h.extract(), e0)
+    for t, vals in enumerate(synth.value_sequence(a, 4)):
+        say("refactor step %d" % t)
+        at = a.with_values(vals)
+        st = h.refactor(vals)
+        ref = orc.refactor(at, order, e0.piv, update_order=orc.ORDER_ASCENDING)
+        if ref.status == 0:
+            assert st == bk.OK
+            compare_exact(h.extract(), ref)
+        else:
+            assert st == bk.REFACTOR_FELL_BACK
+            compare_exact(h.extract(), orc.factor(at, order, update_order=orc.ORDER_ASCENDING))
+            e0 = h.extract()
+        b = synth.rhs(a.n, 1, ident=t)
+        assert orc.residual(at, h.solve(b), b) <= RES_TOL
+
+
+def test_refactor_fallback_forced(bk, orc):
+    a = synth.gen_mna(400, seed=10)
+    order = orc.Ordering.natural(a.n)
+    h = bk.Handle.symbolic_ordered(a, order.prow, order.qcol, order.blkptr, order.grpptr)
+    h.factor(a.values)
+    e0 = h.extract()
+    vals = a.values.copy()
+    p = e0.piv[0]
+    sel = a.rowind[a.colptr[0]:a.colptr[1]] == p
+    vals[a.colptr[0]:a.colptr[1]][sel] *= 1e-12
+    say("refactor forced failure")
+    assert h.refactor(vals) == bk.REFACTOR_FELL_BACK
+    at = a.with_values(vals)
+    compare_exact(h.extract(), orc.factor(at, order, update_order=orc.ORDER_ASCENDING))
+    assert h.info()["refactor_fallbacks"] == 1
+
+
+def test_singular_reported(bk, orc):
+    n = 6
+    s = synth.Stream(61)
+    L0 = np.tril(s.integers(-1, 2, n * n).reshape(n, n), -1) + np.eye(n)
+    U0 = np.triu(s.integers(-1, 2, n * n).reshape(n, n), 1) + np.diag(np.where(s.uniform(n) < 0.5, 1.0, -1.0))
+    A = L0 @ U0
+    A[:, 4] = A[:, 2]
+    a = synth.csc_from_dense(A)
+    o = bk.default_options(pivot_tol=1e-300)
+    h = bk.Handle.symbolic_ordered(a, np.arange(n), np.arange(n), [0, n], [0, n], o)
+    with pytest.raises(bk.BaskerError) as e:
+        h.factor(a.values)
+    assert e.value.status == bk.ERR_NUM_SINGULAR
+    assert h.info()["fail_col"] == 4
+
+
+def test_deterministic_repeat(bk, orc):
+    inp = synth.gen_batched_btf(nblocks=300, big=0, seed=7)
+    h = bk.Handle.symbolic(inp.a)
+    h.factor(inp.a.values)
+    e1 = h.extract()
+    h.factor(inp.a.values)
+    e2 = h.extract()
+    compare_exact(e1, orc.Factors(inp.a.n, 0, -1, e2.Lp, e2.Li, e2.Lx, e2.Up, e2.Ui, e2.Ux, e2.piv, None, 0.0))
+
+
+def test_device_pointers(bk, orc):
+    import torch
+    a = synth.gen_mna(500, seed=11)
+    h = bk.Handle.symbolic(a)
+    vals = torch.from_numpy(a.values.copy()).cuda()
+    h.factor(vals)
+    b = synth.rhs(a.n, 2)
+    Bt = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()   # (nrhs, n) rows = columns of B
+    h.solve(Bt)
+    torch.cuda.synchronize()
+    x = Bt.cpu().numpy().T
+    assert orc.residual(a, x, b) <= RES_TOL
