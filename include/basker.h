@@ -88,7 +88,10 @@ typedef struct {
   int32_t refactor_fallbacks;
   int32_t pool_regrows;
   int32_t nd_blocks;
-  int32_t reserved[15];
+  int32_t nlevels;           /* factor level sets (ND tree height + 1, or 1 without ND) */
+  int32_t solve_levels;      /* level sets of the block back-substitution */
+  int64_t crit_cols;         /* columns on the factor's critical path: sum over levels of the largest segment */
+  int32_t reserved[11];
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */

@@ -47,7 +47,8 @@ class basker_info_t(ctypes.Structure):
                 ("solve_kernel_ms", ctypes.c_double), ("scatter_kernel_ms", ctypes.c_double),
                 ("factor_calls", ctypes.c_int32), ("refactor_calls", ctypes.c_int32),
                 ("refactor_fallbacks", ctypes.c_int32), ("pool_regrows", ctypes.c_int32),
-                ("nd_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 15)]
+                ("nd_blocks", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("solve_levels", ctypes.c_int32),
+                ("crit_cols", ctypes.c_int64), ("reserved", ctypes.c_int32 * 11)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

@@ -53,12 +53,11 @@ struct basker_ctx {
   Plan plan;
   std::string err;
   // plan on device
-  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, parent, nchild, ready;
-  DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, bdep_cnt, bdep_ptr, bdep_idx, bready;
-  std::vector<int32_t> h_bready;
+  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, seg_c0, seg_c1, lvl_seg, lvl_ctr;
+  DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, blvl_blk, blvl_ctr;
   // numeric state
   DBuf<double> vals, Rx, OTx;
-  DBuf<int32_t> done, queue, ctrs, pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
+  DBuf<int32_t> pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
   DBuf<int32_t> Li, Ui;
   DBuf<double> Lx, Ux;
   DBuf<unsigned long long> pool;
@@ -67,7 +66,7 @@ struct basker_ctx {
   int gws_slots = 0;
   int grid = 0;
   // solve scratch
-  DBuf<int32_t> bdone, bqueue, bctrs, sstatus;
+
   DBuf<double> W, Z, Bdev;
   bool factored = false;
   int64_t lnz = 0, unz = 0;
@@ -148,59 +147,30 @@ static basker_status upload_plan(basker_ctx* h) {
         fillp[i]++;
       }
   }
-  // block dependencies: block b reads z of later blocks c; dependents of c are b
   const int nb = (int)P.blkptr.size() - 1;
-  std::vector<int32_t> blk(n);
-  for (int b = 0; b < nb; b++)
-    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk[k] = b;
-  std::vector<int32_t> bcnt(nb, 0), bptr(nb + 1, 0), bidx;
-  std::vector<std::pair<int32_t, int32_t>> edges;  // (c, b)
-  {
-    std::vector<int32_t> seen(nb, -1);
-    for (int b = 0; b < nb; b++) {
-      for (int i = P.blkptr[b]; i < P.blkptr[b + 1]; i++)
-        for (int32_t q = OTp[i]; q < OTp[i + 1]; q++) {
-          int c = blk[OTj[q]];
-          if (seen[c] != b) { seen[c] = b; bcnt[b]++; edges.push_back({c, b}); }
-        }
-    }
-  }
-  for (auto& e : edges) bptr[e.first + 1]++;
-  for (int c = 0; c < nb; c++) bptr[c + 1] += bptr[c];
-  bidx.resize(edges.size());
-  {
-    std::vector<int32_t> fp(bptr.begin(), bptr.end() - 1);
-    for (auto& e : edges) bidx[fp[e.first]++] = e.second;
-  }
-  h->h_bready.clear();
-  for (int b = nb - 1; b >= 0; b--)
-    if (bcnt[b] == 0) h->h_bready.push_back(b);
-  // sizes > 0 for every buffer
+  const int nlev = (int)P.lvl_ptr.size() - 1;
+  const int nblev = (int)P.blvl_ptr.size() - 1;
   HIPCHK(h, h->Rp.upload(P.Rp, s));
   HIPCHK(h, h->Ri.upload(P.Ri, s));
   HIPCHK(h, h->Rmap.upload(P.Rmap, s));
   HIPCHK(h, h->grp_lo.upload(glo, s));
   HIPCHK(h, h->grp_hi.upload(ghi, s));
-  HIPCHK(h, h->parent.upload(P.parent, s));
-  HIPCHK(h, h->nchild.upload(P.nchild, s));
-  HIPCHK(h, h->ready.upload(P.ready, s));
+  HIPCHK(h, h->seg_c0.upload(P.seg_c0, s));
+  HIPCHK(h, h->seg_c1.upload(P.seg_c1, s));
+  HIPCHK(h, h->lvl_seg.upload(P.lvl_seg, s));
+  HIPCHK(h, h->lvl_ctr.reserve(std::max(nlev, 1)));
   HIPCHK(h, h->OTp.upload(OTp, s));
   HIPCHK(h, h->OTj.upload(OTj, s));
   HIPCHK(h, h->OTmap.upload(OTmap, s));
   HIPCHK(h, h->prow.upload(P.prow, s));
   HIPCHK(h, h->qcol.upload(P.qcol, s));
   HIPCHK(h, h->blkptr.upload(P.blkptr, s));
-  HIPCHK(h, h->bdep_cnt.upload(bcnt, s));
-  HIPCHK(h, h->bdep_ptr.upload(bptr, s));
-  HIPCHK(h, h->bdep_idx.upload(bidx, s));
-  HIPCHK(h, h->bready.upload(h->h_bready, s));
+  HIPCHK(h, h->blvl_blk.upload(P.blvl_blk, s));
+  HIPCHK(h, h->blvl_ctr.reserve(std::max(nblev, 1)));
   const int64_t nnzd = (int64_t)P.Ri.size();
   HIPCHK(h, h->vals.reserve(P.nnz));
   HIPCHK(h, h->Rx.reserve(nnzd));
   HIPCHK(h, h->OTx.reserve((int64_t)OTj.size()));
-  HIPCHK(h, h->done.reserve(n));
-  HIPCHK(h, h->queue.reserve(n));
-  HIPCHK(h, h->ctrs.reserve(4));
   HIPCHK(h, h->pinv.reserve(n));
   HIPCHK(h, h->piv.reserve(n));
   HIPCHK(h, h->Lbeg.reserve(n));
@@ -209,10 +179,7 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->Ucnt.reserve(n));
   HIPCHK(h, h->status.reserve(ST_WORDS));
   HIPCHK(h, h->pool.reserve(2));
-  HIPCHK(h, h->bdone.reserve(nb));
-  HIPCHK(h, h->bqueue.reserve(nb));
-  HIPCHK(h, h->bctrs.reserve(4));
-  HIPCHK(h, h->sstatus.reserve(4));
+  (void)nb;
   // L/U pools
   double cf = h->opt.capacity_factor > 0 ? h->opt.capacity_factor : 6.0;
   int64_t cap = (int64_t)(cf * (double)nnzd) + n + 64;
@@ -222,7 +189,9 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->Ui.reserve(cap));
   HIPCHK(h, h->Ux.reserve(cap));
   // persistent grid and the global fallback workspace (one region per workgroup)
-  int grid = std::min(n > 0 ? n : 1, kNumCu * kWavesPerCu);
+  int maxseg = 1;
+  for (int l = 0; l < nlev; l++) maxseg = std::max(maxseg, P.lvl_ptr[l + 1] - P.lvl_ptr[l]);
+  int grid = std::min(maxseg, kNumCu * kWavesPerCu);
   h->grid = grid;
   h->gws_slots = 1 << 14;
   h->gws_stride = ((48LL * h->gws_slots + 16 + 255) / 256) * 256;
@@ -273,6 +242,9 @@ static void fill_info_static(basker_ctx* h) {
   I.max_depth = P.max_depth;
   I.bottleneck = P.bottleneck;
   I.nd_blocks = P.n_nd_blocks;
+  I.crit_cols = P.crit_cols;
+  I.nlevels = (int32_t)P.lvl_ptr.size() - 1;
+  I.solve_levels = (int32_t)P.blvl_ptr.size() - 1;
   I.fail_col = -1;
 }
 
@@ -329,8 +301,7 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.n = h->plan.n;
   a.Rp = h->Rp.p; a.Ri = h->Ri.p; a.Rx = h->Rx.p;
   a.grp_lo = h->grp_lo.p; a.grp_hi = h->grp_hi.p;
-  a.parent = h->parent.p; a.nchild = h->nchild.p;
-  a.done = h->done.p; a.queue = h->queue.p; a.ctrs = h->ctrs.p;
+  a.seg_c0 = h->seg_c0.p; a.seg_c1 = h->seg_c1.p; a.lvl_seg = h->lvl_seg.p; a.lvl_ctr = h->lvl_ctr.p;
   a.pinv = h->pinv.p; a.piv = h->piv.p;
   a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p;
   a.Li = h->Li.p; a.Lx = h->Lx.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
@@ -364,9 +335,17 @@ static basker_status stage_values(basker_ctx* h, const double* values, int32_t o
 static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st, unsigned long long* poolc) {
   hipStream_t s = h->stream;
   FactorArgs a = factor_args(h, refactor);
-  HIPCHK(h, launch_factor_init(a, h->ready.p, (int32_t)h->plan.ready.size(), s));
+  const Plan& P = h->plan;
+  const int nlev = (int)P.lvl_ptr.size() - 1;
+  HIPCHK(h, launch_factor_init(a, nlev, s));
   HIPCHK(h, hipEventRecord(h->ev[0], s));
-  HIPCHK(h, launch_factor(a, h->grid, s));
+  for (int l = 0; l < nlev; l++) {
+    a.level = l;
+    a.lvl_begin = P.lvl_ptr[l];
+    a.lvl_end = P.lvl_ptr[l + 1];
+    const int grid = std::min(a.lvl_end - a.lvl_begin, h->grid);
+    if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
+  }
   HIPCHK(h, hipEventRecord(h->ev[1], s));
   HIPCHK(h, hipMemcpyAsync(st, h->status.p, sizeof(int32_t) * ST_WORDS, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(poolc, h->pool.p, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, s));
@@ -469,29 +448,34 @@ extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, 
   }
   SolveArgs a{};
   a.n = n;
-  a.nblk = (int32_t)h->plan.blkptr.size() - 1;
   a.nrhs = nrhs;
   a.ldb = ld;
   a.blkptr = h->blkptr.p;
+  a.blvl_blk = h->blvl_blk.p;
+  a.lvl_ctr = h->blvl_ctr.p;
   a.piv = h->piv.p;
   a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Li = h->Li.p; a.Lx = h->Lx.p;
   a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
   a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
-  a.bdep_cnt = h->bdep_cnt.p; a.bdep_ptr = h->bdep_ptr.p; a.bdep_idx = h->bdep_idx.p;
-  a.bdone = h->bdone.p; a.queue = h->bqueue.p; a.ctrs = h->bctrs.p; a.status = h->sstatus.p;
   a.prow = h->prow.p; a.qcol = h->qcol.p;
   a.B = dB; a.W = h->W.p; a.Z = h->Z.p;
-  const int grid = std::min(a.nblk, kNumCu * kWavesPerCu);
+  const Plan& P = h->plan;
+  const int nblev = (int)P.blvl_ptr.size() - 1;
+  HIPCHK(h, launch_fill_i32(h->blvl_ctr.p, 0, std::max(nblev, 1), s));
   HIPCHK(h, hipEventRecord(h->ev[2], s));
-  HIPCHK(h, launch_solve(a, h->bready.p, (int32_t)h->h_bready.size(), grid, s));
+  for (int l = 0; l < nblev; l++) {
+    a.level = l;
+    a.lvl_begin = P.blvl_ptr[l];
+    a.lvl_end = P.blvl_ptr[l + 1];
+    const int grid = std::min(a.lvl_end - a.lvl_begin, kNumCu * kWavesPerCu);
+    if (grid > 0) HIPCHK(h, launch_solve_level(a, grid, s));
+  }
+  HIPCHK(h, launch_solve_finish(a, s));
   HIPCHK(h, hipEventRecord(h->ev[3], s));
   if (!B_on_device)
     HIPCHK(h, hipMemcpy2DAsync(B, sizeof(double) * (size_t)ldb, h->Bdev.p, sizeof(double) * n, sizeof(double) * n,
                                nrhs, hipMemcpyDeviceToHost, s));
-  int32_t sst = 0;
-  HIPCHK(h, hipMemcpyAsync(&sst, h->sstatus.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
-  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve kernel stalled");
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev[2], h->ev[3]) == hipSuccess) h->info.solve_kernel_ms = ms;
   return BASKER_OK;

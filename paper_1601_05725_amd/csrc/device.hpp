@@ -5,6 +5,12 @@
 
 #include <cstdint>
 
+// LDS declaration used by the kernels (a CPU debug build of the sources may redefine
+// it to give every emulated workgroup its own copy)
+#ifndef BASKER_SHARED
+#define BASKER_SHARED(type, name) __shared__ type name
+#endif
+
 namespace basker {
 
 constexpr int kWave = 64;
@@ -17,9 +23,6 @@ constexpr int kNumCu = 256;
 enum { ST_CODE = 0, ST_FAILCOL = 1, ST_POOL = 2, ST_WS = 3, ST_OFFDIAG = 4, ST_WORDS = 8 };
 enum { DEV_OK = 0, DEV_SINGULAR = 3, DEV_REFACTOR_FAIL = 8, DEV_WORKSPACE = 7, DEV_POOL = 4, DEV_PATTERN = 5,
        DEV_STALL = 9 };
-// bound on the queue waits of the persistent kernels (s_sleep iterations): a wave that
-// waits longer gives up with DEV_STALL instead of spinning forever
-constexpr long long kSpinLimit = 1ll << 26;
 
 struct FactorArgs {
   int32_t n;
@@ -28,11 +31,13 @@ struct FactorArgs {
   const double* Rx;
   const int32_t* grp_lo;   // candidate group of each column: [grp_lo, grp_hi)
   const int32_t* grp_hi;
-  const int32_t* parent;   // dependency forest
-  const int32_t* nchild;
-  int32_t* done;           // children finished, per column
-  int32_t* queue;          // ready queue: n slots (-1 = not yet pushed)
-  int32_t* ctrs;           // [0] head, [1] tail
+  const int32_t* seg_c0;   // segments: column ranges factored by one wave in order
+  const int32_t* seg_c1;
+  const int32_t* lvl_seg;  // segments of the launched level: lvl_seg[lvl_begin .. lvl_end)
+  int32_t lvl_begin;
+  int32_t lvl_end;
+  int32_t* lvl_ctr;        // one pop counter per level (zeroed before the level)
+  int32_t level;
   int32_t* pinv;           // R row -> column it pivots (-1)
   int32_t* piv;            // column -> R row
   int32_t* Lbeg;           // per-column offsets/counts into the pools
@@ -57,23 +62,20 @@ struct FactorArgs {
 
 struct SolveArgs {
   int32_t n;
-  int32_t nblk;
   int32_t nrhs;
   int32_t ldb;
   const int32_t* blkptr;
+  const int32_t* blvl_blk; // blocks of the launched level: blvl_blk[lvl_begin .. lvl_end)
+  int32_t lvl_begin;
+  int32_t lvl_end;
+  int32_t* lvl_ctr;        // one pop counter per level
+  int32_t level;
   const int32_t* piv;
   const int32_t* Lbeg; const int32_t* Lcnt; const int32_t* Li; const double* Lx;
   const int32_t* Ubeg; const int32_t* Ucnt; const int32_t* Ui; const double* Ux;
   const int32_t* OTp;      // off-diagonal part by R row (CSR): columns and values
   const int32_t* OTj;
   const double* OTx;
-  const int32_t* bdep_cnt; // later blocks each block reads from
-  const int32_t* bdep_ptr; // blocks that read from block c: bdep_idx[bdep_ptr[c] .. bdep_ptr[c+1])
-  const int32_t* bdep_idx;
-  int32_t* bdone;
-  int32_t* queue;          // nblk slots
-  int32_t* ctrs;
-  int32_t* status;         // [0] DEV_STALL if a wait gave up
   const int32_t* prow;
   const int32_t* qcol;
   double* B;               // in/out, column-major (A numbering)
@@ -81,10 +83,11 @@ struct SolveArgs {
   double* Z;               // n x nrhs scratch: solution in R-column numbering
 };
 
-hipError_t launch_factor(const FactorArgs& a, int grid, hipStream_t s);
-hipError_t launch_factor_init(const FactorArgs& a, const int32_t* ready, int32_t nready, hipStream_t s);
+hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
+hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);
-hipError_t launch_solve(const SolveArgs& a, const int32_t* ready, int32_t nready, int grid, hipStream_t s);
+hipError_t launch_solve_level(const SolveArgs& a, int grid, hipStream_t s);
+hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s);
 
 }  // namespace basker

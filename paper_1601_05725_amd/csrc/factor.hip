@@ -14,10 +14,12 @@
 //   store     U(:,k) ascending with the diagonal last, L(:,k) compacted by ballot and
 //             prefix count, both appended to device pools by atomic bump allocation.
 //
-// Columns become ready when all their children in the dependency forest have
-// finished; the last child to finish pushes its parent into the queue.  This is the
-// point-to-point synchronisation of Sec. IV, realised with device-scope
-// release/acquire atomics instead of spinning on volatile flags.
+// Scheduling follows the level sets of Alg. 4: one launch per level, and in a level
+// every wavefront takes whole segments (a BTF block, or one nested-dissection node)
+// from an atomic counter and factors the segment's columns in order.  Segments of a
+// level are independent (separate blocks, or ND nodes whose pivots stay inside the
+// node), so no wavefront ever waits for another inside a launch; the kernel boundary
+// between levels is the only synchronisation across workgroups.
 //
 // Arithmetic matches a serial run that updates in ascending pivot order: every update
 // is a separately rounded multiply and subtract (built with -ffp-contract=off),
@@ -31,9 +33,16 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
-// one workgroup is one wavefront: a workgroup barrier orders the LDS and global
-// accesses of all its lanes.
-__device__ __forceinline__ void wsync() { __syncthreads(); }
+// One workgroup is one wavefront, so no hardware barrier is needed between lanes;
+// what is needed is that every LDS and global access issued before this point has
+// completed before any lane continues (lanes exchange data through LDS and, across
+// columns, through the global arrays).  The fence keeps the compiler from moving
+// memory operations across; the wait drains all outstanding memory counters.
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+}
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = lane_id();
@@ -45,9 +54,6 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-__device__ __forceinline__ int ld_acquire(int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ int ld_relaxed(int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -453,10 +459,10 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
 }
 
 __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
-  __shared__ LdsWs<kLdsSlots> lds;
+  BASKER_SHARED(LdsWs<kLdsSlots>, lds);
   const int lane = lane_id();
   for (int t = lane; t < kLdsSlots; t += 64) lds.key[t] = -1;
-  if (lane == 0) { lds.cnt[0] = 0; lds.cnt[1] = 0; lds.cnt[2] = 0; }
+  if (lane == 0) { lds.cnt[0] = 0; lds.cnt[1] = 0; lds.cnt[2] = 0; lds.cnt[3] = 0; }
   Ws wl;
   wl.key = lds.key; wl.val = lds.val; wl.pv = lds.pv; wl.ins = lds.ins; wl.pj = lds.pj;
   wl.ps = lds.ps; wl.pb = lds.pb; wl.pc = lds.pc; wl.sk = lds.sk; wl.cnt = lds.cnt;
@@ -480,26 +486,16 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.shift = 32 - __builtin_ctz((unsigned)H);
   }
   wsync();
+  const int nseg = a.lvl_end - a.lvl_begin;
   while (true) {
-    int pos = 0;
-    if (lane == 0) pos = atomicAdd(&a.ctrs[0], 1);
-    pos = __shfl(pos, 0, 64);
-    if (pos >= a.n) break;
-    int k = -1;
-    if (lane == 0) {
-      long long spins = 0;
-      while ((k = ld_acquire(&a.queue[pos])) < 0) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          atomicMax(&a.status[ST_CODE], DEV_STALL);
-          break;
-        }
-      }
-    }
-    k = __shfl(k, 0, 64);
-    wsync();
-    if (k < 0) break;
-    if (ld_relaxed(&a.status[ST_CODE]) == DEV_OK) {
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(&a.lvl_ctr[a.level], 1);
+    idx = __shfl(idx, 0, 64);
+    if (idx >= nseg) break;
+    const int sg = a.lvl_seg[a.lvl_begin + idx];
+    const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];
+    for (int k = c0; k < c1; k++) {
+      if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) break;
       int rc = factor_column(a, wl, k);
       if (rc == 1) {
         rc = factor_column(a, wg, k);
@@ -509,35 +505,18 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
           a.status[ST_WS] = 1;
         }
       }
-    }
-    // publish column k and release its parent when k is the last child to finish
-    wsync();
-    if (lane == 0) {
-      const int par = a.parent[k];
-      if (par >= 0) {
-        const int old = __hip_atomic_fetch_add(&a.done[par], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == a.nchild[par]) {
-          const int slot = __hip_atomic_fetch_add(&a.ctrs[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&a.queue[slot], par, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
+      // the next column reads this column's pinv/L/U entries written by other lanes
+      wsync();
     }
   }
 }
 
-__global__ void factor_init_kernel(FactorArgs a, const int32_t* ready, int32_t nready) {
+__global__ void factor_init_kernel(FactorArgs a, int32_t nlevels) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n) {
-    a.done[i] = 0;
-    a.queue[i] = i < nready ? ready[i] : -1;
-    if (!a.refactor) a.pinv[i] = -1;
-  }
+  if (i < a.n && !a.refactor) a.pinv[i] = -1;
   if (i < ST_WORDS) a.status[i] = (i == ST_FAILCOL) ? 0x7fffffff : 0;
-  if (i == 0) {
-    a.ctrs[0] = 0;
-    a.ctrs[1] = nready;
-    if (!a.refactor) { a.pool_next[0] = 0; a.pool_next[1] = 0; }
-  }
+  if (i < nlevels) a.lvl_ctr[i] = 0;
+  if (i == 0 && !a.refactor) { a.pool_next[0] = 0; a.pool_next[1] = 0; }
 }
 
 __global__ void scatter_kernel(const double* __restrict__ vals, const int32_t* __restrict__ map,
@@ -553,14 +532,16 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t cnt) {
 
 }  // namespace
 
-hipError_t launch_factor_init(const FactorArgs& a, const int32_t* ready, int32_t nready, hipStream_t s) {
-  const int64_t cnt = a.n > ST_WORDS ? a.n : ST_WORDS;
+hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s) {
+  int64_t cnt = a.n;
+  if (cnt < ST_WORDS) cnt = ST_WORDS;
+  if (cnt < nlevels) cnt = nlevels;
   const int blocks = (int)((cnt + 255) / 256);
-  hipLaunchKernelGGL(factor_init_kernel, dim3(blocks), dim3(256), 0, s, a, ready, nready);
+  hipLaunchKernelGGL(factor_init_kernel, dim3(blocks), dim3(256), 0, s, a, nlevels);
   return hipGetLastError();
 }
 
-hipError_t launch_factor(const FactorArgs& a, int grid, hipStream_t s) {
+hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(factor_kernel, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }

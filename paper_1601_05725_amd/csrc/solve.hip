@@ -2,11 +2,11 @@
 //
 // R = A(prow, qcol) is block upper triangular, so block b needs the solution of every
 // later block it couples to: r_b = c_b - sum_{c > b} R_bc z_c, then L w = r(piv) and
-// U z_b = w.  A persistent kernel takes ready blocks from a device queue, one
-// wavefront per block; a block becomes ready when every later block it reads from
-// has finished (completion counters, device-scope release/acquire).  The coupling
-// sums are pulled row by row in a fixed order, and the triangular solves run column
-// by column inside one wave, so results do not depend on scheduling.
+// U z_b = w.  Blocks are grouped in levels (a block's level is one more than the
+// highest level of the later blocks it reads from), one launch per level; inside a
+// launch every wavefront takes whole blocks from an atomic counter.  The coupling sums
+// are pulled row by row in a fixed order and the triangular solves run column by
+// column inside one wave, so results do not depend on scheduling.
 #include "device.hpp"
 
 namespace basker {
@@ -14,30 +14,25 @@ namespace basker {
 namespace {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-__device__ __forceinline__ void wsync() { __syncthreads(); }
+
+// lanes exchange data through global memory between steps: drain every outstanding
+// memory operation and keep the compiler from moving accesses across
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+}
 
 __global__ void __launch_bounds__(64) solve_kernel(SolveArgs a) {
   const int lane = lane_id();
   const int n = a.n;
+  const int nb = a.lvl_end - a.lvl_begin;
   while (true) {
-    int pos = 0;
-    if (lane == 0) pos = atomicAdd(&a.ctrs[0], 1);
-    pos = __shfl(pos, 0, 64);
-    if (pos >= a.nblk) break;
-    int b = -1;
-    if (lane == 0) {
-      long long spins = 0;
-      while ((b = __hip_atomic_load(&a.queue[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) < 0) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          atomicMax(&a.status[0], DEV_STALL);
-          break;
-        }
-      }
-    }
-    b = __shfl(b, 0, 64);
-    wsync();
-    if (b < 0) break;
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(&a.lvl_ctr[a.level], 1);
+    idx = __shfl(idx, 0, 64);
+    if (idx >= nb) break;
+    const int b = a.blvl_blk[a.lvl_begin + idx];
     const int b0 = a.blkptr[b], b1 = a.blkptr[b + 1];
     for (int rhs = 0; rhs < a.nrhs; rhs++) {
       double* W = a.W + (int64_t)rhs * n;
@@ -80,27 +75,7 @@ __global__ void __launch_bounds__(64) solve_kernel(SolveArgs a) {
         wsync();
       }
     }
-    // release the earlier blocks that read from this one
-    if (lane == 0) {
-      for (int q = a.bdep_ptr[b]; q < a.bdep_ptr[b + 1]; q++) {
-        const int d = a.bdep_idx[q];
-        const int old = __hip_atomic_fetch_add(&a.bdone[d], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == a.bdep_cnt[d]) {
-          const int slot = __hip_atomic_fetch_add(&a.ctrs[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&a.queue[slot], d, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-    }
   }
-}
-
-__global__ void solve_init_kernel(SolveArgs a, const int32_t* ready, int32_t nready) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.nblk) {
-    a.bdone[i] = 0;
-    a.queue[i] = i < nready ? ready[i] : -1;
-  }
-  if (i == 0) { a.ctrs[0] = 0; a.ctrs[1] = nready; a.status[0] = 0; }
 }
 
 __global__ void solve_unpermute_kernel(SolveArgs a) {
@@ -115,10 +90,12 @@ __global__ void solve_unpermute_kernel(SolveArgs a) {
 
 }  // namespace
 
-hipError_t launch_solve(const SolveArgs& a, const int32_t* ready, int32_t nready, int grid, hipStream_t s) {
-  const int nb = a.nblk > 1 ? a.nblk : 1;
-  hipLaunchKernelGGL(solve_init_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a, ready, nready);
+hipError_t launch_solve_level(const SolveArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(solve_kernel, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s) {
   const int64_t total = (int64_t)a.n * a.nrhs;
   if (total > 0)
     hipLaunchKernelGGL(solve_unpermute_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);

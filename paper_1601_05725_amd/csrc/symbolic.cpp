@@ -584,6 +584,57 @@ void finish_schedule(Plan& P) {
     for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) P.col_grp[k] = (int32_t)g;
 }
 
+// Level lists of the factor segments (largest first inside a level) and of the
+// solve's block back-substitution: block b reads the solution of the later blocks its
+// off-diagonal entries touch, so level(b) = 1 + max level of those blocks.
+void build_levels(Plan& P) {
+  const int ns = (int)P.seg_c0.size();
+  int nl = 0;
+  for (int s = 0; s < ns; s++) nl = std::max(nl, P.seg_level[s] + 1);
+  P.lvl_ptr.assign(nl + 1, 0);
+  for (int s = 0; s < ns; s++) P.lvl_ptr[P.seg_level[s] + 1]++;
+  for (int l = 0; l < nl; l++) P.lvl_ptr[l + 1] += P.lvl_ptr[l];
+  P.lvl_seg.assign(ns, 0);
+  {
+    std::vector<int32_t> fp(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
+    for (int s = 0; s < ns; s++) P.lvl_seg[fp[P.seg_level[s]]++] = s;
+  }
+  P.crit_cols = 0;
+  for (int l = 0; l < nl; l++) {
+    auto b = P.lvl_seg.begin() + P.lvl_ptr[l], e = P.lvl_seg.begin() + P.lvl_ptr[l + 1];
+    std::stable_sort(b, e, [&](int x, int y) { return P.seg_c1[x] - P.seg_c0[x] > P.seg_c1[y] - P.seg_c0[y]; });
+    if (b != e) P.crit_cols += P.seg_c1[*b] - P.seg_c0[*b];
+  }
+  // solve levels over blocks (later blocks first)
+  const int nb = (int)P.blkptr.size() - 1;
+  std::vector<int32_t> blk(P.n);
+  for (int b = 0; b < nb; b++)
+    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk[k] = b;
+  std::vector<int32_t> lev(nb, 0);
+  int maxl = 0;
+  // entries of column k (block c) in rows of block b < c: b waits for c
+  // compute with the column-oriented off-diagonal part: for c from last to first, every
+  // row block b of column entries of c gets lev[b] >= lev[c] + 1
+  for (int c = nb - 1; c >= 0; c--) {
+    for (int k = P.blkptr[c]; k < P.blkptr[c + 1]; k++)
+      for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) {
+        int b = blk[P.Oi[q]];
+        if (lev[b] < lev[c] + 1) lev[b] = lev[c] + 1;
+      }
+    maxl = std::max(maxl, lev[c]);
+  }
+  P.blvl_ptr.assign(maxl + 2, 0);
+  for (int b = 0; b < nb; b++) P.blvl_ptr[lev[b] + 1]++;
+  for (int l = 0; l <= maxl; l++) P.blvl_ptr[l + 1] += P.blvl_ptr[l];
+  P.blvl_blk.assign(nb, 0);
+  std::vector<int32_t> fp(P.blvl_ptr.begin(), P.blvl_ptr.end() - 1);
+  for (int b = nb - 1; b >= 0; b--) P.blvl_blk[fp[lev[b]]++] = b;
+  for (int l = 0; l <= maxl; l++) {
+    auto bb = P.blvl_blk.begin() + P.blvl_ptr[l], ee = P.blvl_blk.begin() + P.blvl_ptr[l + 1];
+    std::stable_sort(bb, ee, [&](int x, int y) { return P.blkptr[x + 1] - P.blkptr[x] > P.blkptr[y + 1] - P.blkptr[y]; });
+  }
+}
+
 }  // namespace
 
 int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
@@ -620,7 +671,7 @@ int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
   P.grpptr.assign(1, 0);
   std::vector<int64_t> xadj;
   std::vector<int32_t> adj;
-  struct NdBlockInfo { int b; std::vector<int32_t> node_size, node_parent; std::vector<char> node_leaf; };
+  struct NdBlockInfo { int b; std::vector<int32_t> node_size, node_parent, node_level; std::vector<char> node_leaf; };
   std::vector<NdBlockInfo> ndinfo;
   for (size_t b = 0; b + 1 < blk0.size(); b++) {
     int s0 = blk0[b], s1 = blk0[b + 1], sz = s1 - s0;
@@ -661,6 +712,7 @@ int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
         info.node_size.push_back((int32_t)vs.size());
         info.node_parent.push_back(npar[t]);
         info.node_leaf.push_back(nleaf[t]);
+        info.node_level.push_back(nlev[t]);
       }
       ndinfo.push_back(std::move(info));
       P.n_nd_blocks++;
@@ -745,6 +797,27 @@ int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
       if (u >= 0) P.grp_parent[group_at(c0[t])] = group_at(c0[u]);
     }
   }
+  // segments and levels
+  {
+    std::vector<int32_t> seg_of_block_level;  // level per segment
+    std::vector<char> is_nd_b(P.blkptr.size(), 0);
+    std::vector<const NdBlockInfo*> info_of(P.blkptr.size(), nullptr);
+    for (auto& info : ndinfo) { is_nd_b[info.b] = 1; info_of[info.b] = &info; }
+    for (size_t b = 0; b + 1 < P.blkptr.size(); b++) {
+      if (!is_nd_b[b]) {
+        P.seg_c0.push_back(P.blkptr[b]); P.seg_c1.push_back(P.blkptr[b + 1]); P.seg_level.push_back(0);
+        continue;
+      }
+      const NdBlockInfo& info = *info_of[b];
+      int c = P.blkptr[b];
+      for (size_t t = 0; t < info.node_size.size(); t++) {
+        if (info.node_size[t] == 0) continue;
+        P.seg_c0.push_back(c); P.seg_c1.push_back(c + info.node_size[t]); P.seg_level.push_back(info.node_level[t]);
+        c += info.node_size[t];
+      }
+    }
+  }
+  build_levels(P);
   return 0;
 }
 
@@ -788,6 +861,10 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
   for (int b = 0; b < nblk; b++) block_col_etree(P.blkptr[b], P.blkptr[b + 1], P.Rp, P.Ri, P.parent, prev, anc);
   finish_schedule(P);
   P.grp_parent.assign(P.grpptr.size() - 1, -1);
+  for (int b = 0; b < nblk; b++) {
+    P.seg_c0.push_back(P.blkptr[b]); P.seg_c1.push_back(P.blkptr[b + 1]); P.seg_level.push_back(0);
+  }
+  build_levels(P);
   return 0;
 }
 

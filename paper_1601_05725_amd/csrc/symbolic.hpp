@@ -45,6 +45,15 @@ struct Plan {
   std::vector<int32_t> parent, nchild, ready;
   std::vector<int32_t> depth;
   std::vector<NdNode> nd_nodes;
+  // segments: contiguous column ranges factored by one wavefront each, column by
+  // column.  A non-ND block is one segment at level 0; an ND node is one segment at
+  // its tree level (leaves 0).  Levels run one after another (Alg. 4's level sets);
+  // segments of one level are independent.
+  std::vector<int32_t> seg_c0, seg_c1, seg_level;
+  std::vector<int32_t> lvl_ptr, lvl_seg;      // segments of level l: lvl_seg[lvl_ptr[l] .. lvl_ptr[l+1])
+  int64_t crit_cols = 0;                      // sum over levels of the largest segment
+  // solve: block levels of the back-substitution (blocks of a level are independent)
+  std::vector<int32_t> blvl_ptr, blvl_blk;
   int struct_rank = 0;
   double bottleneck = 0.0;
   int max_depth = 0;
