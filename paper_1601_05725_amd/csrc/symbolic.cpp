@@ -25,13 +25,14 @@ bool validate_csc(int n, const int32_t* Ap, const int32_t* Ai, std::string& err)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Maximum matching by depth-first augmenting paths with a cheap-assignment
-// lookahead (Duff's MC21 scheme).  Entries with |a| < thresh are not usable.
+// Maximum matching: a greedy start (diagonal first, then any free row), then a
+// shortest augmenting path (breadth first) from every column left unmatched.
+// Entries with |a| < thresh are not usable.
 // ---------------------------------------------------------------------------
 int max_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax, double thresh,
                  std::vector<int32_t>& m) {
   auto usable = [&](int32_t p) { return !Ax || std::fabs(Ax[p]) >= thresh; };
-  std::vector<int32_t> col_of_row(n, -1), cheap(n), visited(n, -1), cstack(n), pos(n);
+  std::vector<int32_t> col_of_row(n, -1), visited(n, -1), cstack(n);
   if ((int)m.size() != n) m.assign(n, -1);
   int matched = 0;
   for (int j = 0; j < n; j++) {
@@ -43,44 +44,55 @@ int max_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax, 
     }
     if (ok) { col_of_row[i] = j; matched++; } else m[j] = -1;
   }
-  for (int j = 0; j < n; j++) cheap[j] = Ap[j];
+  // greedy start: the diagonal entry where it is usable, then any free usable row,
+  // so that the augmenting searches below only handle the few remaining columns
+  for (int j = 0; j < n; j++) {
+    if (m[j] >= 0 || col_of_row[j] >= 0) continue;
+    for (int32_t p = Ap[j]; p < Ap[j + 1]; p++)
+      if (Ai[p] == j) {
+        if (usable(p)) { m[j] = j; col_of_row[j] = j; matched++; }
+        break;
+      }
+  }
+  for (int j = 0; j < n; j++) {
+    if (m[j] >= 0) continue;
+    for (int32_t p = Ap[j]; p < Ap[j + 1]; p++)
+      if (usable(p) && col_of_row[Ai[p]] < 0) { m[j] = Ai[p]; col_of_row[Ai[p]] = j; matched++; break; }
+  }
+  // shortest augmenting path from every unmatched column (breadth-first over
+  // alternating paths: column -> row -> the row's matched column)
+  std::vector<int32_t> prev_col(n, -1), via_row(n, -1);
   for (int j0 = 0; j0 < n; j0++) {
     if (m[j0] >= 0) continue;
-    int head = 0;
-    cstack[0] = j0;
-    pos[j0] = Ap[j0];
+    int head = 0, tail = 0;
+    cstack[tail++] = j0;
     visited[j0] = j0;
-    int32_t found = -1;
-    while (head >= 0) {
-      int32_t j = cstack[head];
-      for (; cheap[j] < Ap[j + 1]; cheap[j]++) {
-        int32_t p = cheap[j];
-        if (usable(p) && col_of_row[Ai[p]] < 0) { found = Ai[p]; break; }
-      }
-      if (found >= 0) break;
-      bool pushed = false;
-      for (int32_t p = pos[j]; p < Ap[j + 1]; p++) {
+    prev_col[j0] = -1;
+    int32_t found = -1, found_col = -1;
+    while (head < tail && found < 0) {
+      int32_t j = cstack[head++];
+      for (int32_t p = Ap[j]; p < Ap[j + 1]; p++) {
         if (!usable(p)) continue;
-        int32_t jj = col_of_row[Ai[p]];
-        if (jj >= 0 && visited[jj] != j0) {
-          pos[j] = p + 1;
+        int32_t i = Ai[p];
+        int32_t jj = col_of_row[i];
+        if (jj < 0) { found = i; found_col = j; break; }
+        if (visited[jj] != j0) {
           visited[jj] = j0;
-          pos[jj] = Ap[jj];
-          cstack[++head] = jj;
-          pushed = true;
-          break;
+          prev_col[jj] = j;
+          via_row[jj] = i;
+          cstack[tail++] = jj;
         }
       }
-      if (!pushed) { pos[j] = Ap[j + 1]; head--; }
     }
     if (found >= 0) {
-      int32_t r = found;
-      for (int h = head; h >= 0; h--) {
-        int32_t c = cstack[h];
+      // flip the path: found_col takes `found`, each column hands its row to the next
+      int32_t c = found_col, r = found;
+      while (c >= 0) {
         int32_t old = m[c];
         m[c] = r;
         col_of_row[r] = c;
         r = old;
+        c = prev_col[c];
       }
       matched++;
     }
@@ -402,105 +414,342 @@ static int bfs_levels(NdBuild& B, int id, int src, const std::vector<int32_t>& v
   return last;
 }
 
+// ---------------------------------------------------------------------------
+// Multilevel bisection (the scheme of Karypis and Kumar's METIS, restated):
+// coarsen by heavy-edge matching, split the coarsest graph by greedy growing,
+// refine with Fiduccia-Mattheyses moves on every level while projecting back, and
+// turn the final edge cut into a vertex separator by a minimum vertex cover of the
+// cut edges (Koenig's theorem on the bipartite cut graph).
+// ---------------------------------------------------------------------------
+struct WGraph {
+  int n = 0;
+  std::vector<int64_t> xadj;
+  std::vector<int32_t> adj, ewgt;
+  std::vector<int32_t> vwgt;
+};
+
+static uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// heavy-edge matching; returns the coarse graph and the fine->coarse map
+static bool coarsen(const WGraph& g, WGraph& c, std::vector<int32_t>& cmap, uint64_t seed) {
+  const int n = g.n;
+  std::vector<int32_t> order(n), match(n, -1);
+  for (int i = 0; i < n; i++) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    uint64_t ha = mix64(seed ^ (uint64_t)a), hb = mix64(seed ^ (uint64_t)b);
+    return ha < hb;
+  });
+  for (int v : order) {
+    if (match[v] >= 0) continue;
+    int best = -1, bw = -1;
+    for (int64_t p = g.xadj[v]; p < g.xadj[v + 1]; p++) {
+      int u = g.adj[p];
+      if (match[u] < 0 && u != v && g.ewgt[p] > bw) { bw = g.ewgt[p]; best = u; }
+    }
+    if (best >= 0) { match[v] = best; match[best] = v; }
+    else match[v] = v;
+  }
+  cmap.assign(n, -1);
+  int nc = 0;
+  for (int v = 0; v < n; v++) {
+    if (cmap[v] >= 0) continue;
+    cmap[v] = nc;
+    if (match[v] != v) cmap[match[v]] = nc;
+    nc++;
+  }
+  if (nc > (int)(0.95 * n)) return false;
+  c.n = nc;
+  c.vwgt.assign(nc, 0);
+  for (int v = 0; v < n; v++) c.vwgt[cmap[v]] += g.vwgt[v];
+  // coarse adjacency with summed edge weights
+  std::vector<int32_t> mark(nc, -1), pos(nc, 0);
+  std::vector<std::vector<int32_t>> members(nc);
+  for (int v = 0; v < n; v++) members[cmap[v]].push_back(v);
+  c.xadj.assign(nc + 1, 0);
+  c.adj.clear();
+  c.ewgt.clear();
+  for (int cv = 0; cv < nc; cv++) {
+    size_t start = c.adj.size();
+    for (int v : members[cv])
+      for (int64_t p = g.xadj[v]; p < g.xadj[v + 1]; p++) {
+        int cu = cmap[g.adj[p]];
+        if (cu == cv) continue;
+        if (mark[cu] != cv) {
+          mark[cu] = cv;
+          pos[cu] = (int32_t)c.adj.size();
+          c.adj.push_back(cu);
+          c.ewgt.push_back(g.ewgt[p]);
+        } else {
+          c.ewgt[pos[cu]] += g.ewgt[p];
+        }
+      }
+    (void)start;
+    c.xadj[cv + 1] = (int64_t)c.adj.size();
+  }
+  return true;
+}
+
+// Fiduccia-Mattheyses refinement of a 2-way partition (side 0/1) with balance
+// max side weight <= maxw.  Moves are tried greedily by gain; each pass keeps the
+// best prefix of moves.
+static void fm_refine(const WGraph& g, std::vector<char>& side, int64_t maxw, int passes) {
+  const int n = g.n;
+  int64_t w[2] = {0, 0};
+  for (int v = 0; v < n; v++) w[(int)side[v]] += g.vwgt[v];
+  std::vector<int64_t> gain(n);
+  std::vector<char> locked(n);
+  for (int pass = 0; pass < passes; pass++) {
+    for (int v = 0; v < n; v++) {
+      int64_t ext = 0, in = 0;
+      for (int64_t p = g.xadj[v]; p < g.xadj[v + 1]; p++) (side[g.adj[p]] == side[v] ? in : ext) += g.ewgt[p];
+      gain[v] = ext - in;
+    }
+    std::fill(locked.begin(), locked.end(), 0);
+    // boundary-driven priority queue (max gain; ties by vertex id)
+    std::vector<std::pair<int64_t, int32_t>> heap;
+    auto push = [&](int v) { heap.push_back({gain[v], -v}); std::push_heap(heap.begin(), heap.end()); };
+    for (int v = 0; v < n; v++) {
+      bool bnd = false;
+      for (int64_t p = g.xadj[v]; p < g.xadj[v + 1] && !bnd; p++) bnd = side[g.adj[p]] != side[v];
+      if (bnd) push(v);
+    }
+    std::vector<int32_t> moved;
+    int64_t cur = 0, best = 0;
+    size_t best_len = 0;
+    int stall = 0;
+    while (!heap.empty() && stall < 200) {
+      std::pop_heap(heap.begin(), heap.end());
+      auto top = heap.back();
+      heap.pop_back();
+      int v = -top.second;
+      if (locked[v] || top.first != gain[v]) continue;
+      int from = side[v], to = 1 - from;
+      if (w[to] + g.vwgt[v] > maxw) continue;
+      locked[v] = 1;
+      side[v] = (char)to;
+      w[from] -= g.vwgt[v];
+      w[to] += g.vwgt[v];
+      cur += gain[v];
+      moved.push_back(v);
+      for (int64_t p = g.xadj[v]; p < g.xadj[v + 1]; p++) {
+        int u = g.adj[p];
+        if (locked[u]) continue;
+        gain[u] += (side[u] == to) ? -2 * g.ewgt[p] : 2 * g.ewgt[p];
+        push(u);
+      }
+      if (cur > best) { best = cur; best_len = moved.size(); stall = 0; }
+      else stall++;
+    }
+    // undo the moves after the best prefix
+    for (size_t i = moved.size(); i > best_len; i--) {
+      int v = moved[i - 1];
+      int from = side[v], to = 1 - from;
+      side[v] = (char)to;
+      w[from] -= g.vwgt[v];
+      w[to] += g.vwgt[v];
+    }
+    if (best <= 0) break;
+  }
+}
+
+// Greedy growing from a seed: add the frontier vertex with the largest gain until
+// half of the weight is on side 0.
+static void grow_partition(const WGraph& g, int seed, std::vector<char>& side) {
+  const int n = g.n;
+  int64_t total = 0;
+  for (int v = 0; v < n; v++) total += g.vwgt[v];
+  side.assign(n, 1);
+  std::vector<int64_t> conn(n, 0);
+  std::vector<std::pair<int64_t, int32_t>> heap;
+  int64_t w0 = 0;
+  auto add = [&](int v) {
+    side[v] = 0;
+    w0 += g.vwgt[v];
+    for (int64_t p = g.xadj[v]; p < g.xadj[v + 1]; p++) {
+      int u = g.adj[p];
+      if (side[u] == 1) { conn[u] += g.ewgt[p]; heap.push_back({conn[u], -u}); std::push_heap(heap.begin(), heap.end()); }
+    }
+  };
+  add(seed);
+  while (w0 * 2 < total) {
+    int v = -1;
+    while (!heap.empty()) {
+      std::pop_heap(heap.begin(), heap.end());
+      auto t = heap.back();
+      heap.pop_back();
+      if (side[-t.second] == 1 && t.first == conn[-t.second]) { v = -t.second; break; }
+    }
+    if (v < 0) {  // disconnected remainder: take any vertex
+      for (int u = 0; u < n; u++) if (side[u] == 1) { v = u; break; }
+      if (v < 0) break;
+    }
+    add(v);
+  }
+}
+
+static int64_t cut_weight(const WGraph& g, const std::vector<char>& side) {
+  int64_t c = 0;
+  for (int v = 0; v < g.n; v++)
+    for (int64_t p = g.xadj[v]; p < g.xadj[v + 1]; p++)
+      if (side[g.adj[p]] != side[v]) c += g.ewgt[p];
+  return c / 2;
+}
+
+// 2-way edge partition of g by the multilevel scheme
+static void multilevel_bisect(const WGraph& g0, std::vector<char>& side, uint64_t seed) {
+  std::vector<WGraph> levels;
+  std::vector<std::vector<int32_t>> maps;
+  levels.push_back(g0);
+  while (levels.back().n > 120) {
+    WGraph c;
+    std::vector<int32_t> cmap;
+    if (!coarsen(levels.back(), c, cmap, seed + levels.size())) break;
+    maps.push_back(std::move(cmap));
+    levels.push_back(std::move(c));
+  }
+  const WGraph& gc = levels.back();
+  int64_t total = 0;
+  for (int v = 0; v < gc.n; v++) total += gc.vwgt[v];
+  const double imb = 1.05;
+  int64_t maxw = (int64_t)(imb * (double)total / 2.0) + 1;
+  // best of a few growing seeds at the coarsest level
+  std::vector<char> best_side;
+  int64_t best_cut = INT64_MAX;
+  const int tries = std::min(gc.n, 8);
+  for (int t = 0; t < tries; t++) {
+    int s0 = (int)(mix64(seed * 31 + t) % (uint64_t)gc.n);
+    std::vector<char> sd;
+    grow_partition(gc, s0, sd);
+    fm_refine(gc, sd, maxw, 4);
+    int64_t c = cut_weight(gc, sd);
+    if (c < best_cut) { best_cut = c; best_side = sd; }
+  }
+  side = best_side;
+  for (int l = (int)levels.size() - 2; l >= 0; l--) {
+    const WGraph& g = levels[l];
+    std::vector<char> fine(g.n);
+    for (int v = 0; v < g.n; v++) fine[v] = side[maps[l][v]];
+    side.swap(fine);
+    int64_t tw = 0;
+    for (int v = 0; v < g.n; v++) tw += g.vwgt[v];
+    fm_refine(g, side, (int64_t)(imb * (double)tw / 2.0) + 1, 3);
+  }
+}
+
+// minimum vertex cover of the bipartite graph of cut edges (left = side 0)
+static void cut_vertex_cover(const WGraph& g, const std::vector<char>& side, std::vector<char>& in_sep) {
+  const int n = g.n;
+  in_sep.assign(n, 0);
+  std::vector<int32_t> mate(n, -1);
+  // augmenting paths from every left boundary vertex (Kuhn's algorithm)
+  std::vector<int32_t> seen(n, -1), stack, from_edge;
+  std::vector<int64_t> it(n);
+  for (int v = 0; v < n; v++) {
+    if (side[v] != 0) continue;
+    bool bnd = false;
+    for (int64_t p = g.xadj[v]; p < g.xadj[v + 1] && !bnd; p++) bnd = side[g.adj[p]] == 1;
+    if (!bnd) continue;
+    // DFS over alternating paths: left u -> right w (cut edge) -> left mate[w]
+    stack.assign(1, v);
+    it[v] = g.xadj[v];
+    seen[v] = v;
+    std::vector<int32_t> via;  // right vertex used to reach each stacked left vertex
+    via.assign(1, -1);
+    bool found = false;
+    while (!stack.empty() && !found) {
+      int u = stack.back();
+      bool pushed = false;
+      while (it[u] < g.xadj[u + 1]) {
+        int w = g.adj[it[u]++];
+        if (side[w] != 1) continue;
+        if (mate[w] < 0) {
+          // augment along the stack
+          int r = w;
+          for (int h = (int)stack.size() - 1; h >= 0; h--) {
+            int l = stack[h];
+            int prev = mate[l];
+            mate[l] = r;
+            mate[r] = l;
+            r = prev;
+          }
+          found = true;
+          break;
+        }
+        int l2 = mate[w];
+        if (seen[l2] != v) {
+          seen[l2] = v;
+          it[l2] = g.xadj[l2];
+          stack.push_back(l2);
+          via.push_back(w);
+          pushed = true;
+          break;
+        }
+      }
+      if (!found && !pushed) { stack.pop_back(); via.pop_back(); }
+    }
+  }
+  // Koenig: Z = vertices reachable from unmatched left boundary vertices by alternating paths
+  std::vector<char> inZ(n, 0);
+  std::vector<int32_t> q;
+  for (int v = 0; v < n; v++) {
+    if (side[v] != 0 || mate[v] >= 0) continue;
+    bool bnd = false;
+    for (int64_t p = g.xadj[v]; p < g.xadj[v + 1] && !bnd; p++) bnd = side[g.adj[p]] == 1;
+    if (bnd) { inZ[v] = 1; q.push_back(v); }
+  }
+  for (size_t h = 0; h < q.size(); h++) {
+    int u = q[h];
+    for (int64_t p = g.xadj[u]; p < g.xadj[u + 1]; p++) {
+      int w = g.adj[p];
+      if (side[w] != 1 || inZ[w]) continue;
+      inZ[w] = 1;
+      int l = mate[w];
+      if (l >= 0 && !inZ[l]) { inZ[l] = 1; q.push_back(l); }
+    }
+  }
+  for (int v = 0; v < n; v++) {
+    bool bnd = false;
+    for (int64_t p = g.xadj[v]; p < g.xadj[v + 1] && !bnd; p++) bnd = side[g.adj[p]] != side[v];
+    if (!bnd) continue;
+    if (side[v] == 0 && !inZ[v]) in_sep[v] = 1;
+    if (side[v] == 1 && inZ[v]) in_sep[v] = 1;
+  }
+}
+
 // split `verts` (subset id) into (left, right, sep)
 static void bisect(NdBuild& B, int id, const std::vector<int32_t>& verts, std::vector<int32_t>& left,
                    std::vector<int32_t>& right, std::vector<int32_t>& sep) {
   left.clear(); right.clear(); sep.clear();
   const int m = (int)verts.size();
   if (m == 0) return;
-  int nlev = 0;
-  int far = bfs_levels(B, id, verts[0], verts, &nlev);
-  if ((int)B.queue.size() < m) {
-    // disconnected: whole components to the two sides, smaller ones first to the lighter
-    std::vector<std::vector<int32_t>> comps;
-    std::vector<char> seen(0);
-    for (int v : verts) B.level[v] = -1;
-    for (int v : verts) {
-      if (B.level[v] >= 0) continue;
-      int dummy;
-      (void)dummy;
-      B.queue.clear();
-      B.queue.push_back(v);
-      B.level[v] = 0;
-      size_t h = 0;
-      while (h < B.queue.size()) {
-        int x = B.queue[h++];
-        for (int64_t p = B.xadj[x]; p < B.xadj[x + 1]; p++) {
-          int w = B.adj[p];
-          if (B.part[w] == id && B.level[w] < 0) { B.level[w] = 0; B.queue.push_back(w); }
-        }
-      }
-      comps.push_back(B.queue);
-    }
-    std::stable_sort(comps.begin(), comps.end(),
-                     [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) { return a.size() > b.size(); });
-    for (auto& c : comps) {
-      auto& dst = left.size() <= right.size() ? left : right;
-      dst.insert(dst.end(), c.begin(), c.end());
-    }
-    return;
-  }
-  // pseudo-peripheral vertex: repeat BFS from the farthest vertex while the depth grows
-  int src = far;
-  for (int it = 0; it < 4; it++) {
-    int nl2 = 0;
-    int f2 = bfs_levels(B, id, src, verts, &nl2);
-    if (nl2 <= nlev) break;
-    nlev = nl2;
-    src = f2;
-  }
-  int nl = 0;
-  bfs_levels(B, id, src, verts, &nl);
-  if (nl < 3) {
-    // too shallow to cut by levels: take everything after the first level as the separator
-    for (int v : verts) (B.level[v] == 0 ? left : sep).push_back(v);
-    return;
-  }
-  std::vector<int64_t> cnt(nl, 0);
-  for (int v : verts) cnt[B.level[v]]++;
-  // smallest level whose cumulative count before it lies in [35%, 65%] of m
-  int64_t acc = 0;
-  int best = -1;
-  int64_t bestsz = INT64_MAX;
-  for (int l = 0; l < nl; l++) {
-    if (l > 0 && l < nl - 1 && acc >= (int64_t)(0.35 * m) && acc <= (int64_t)(0.65 * m) && cnt[l] < bestsz) {
-      bestsz = cnt[l];
-      best = l;
-    }
-    acc += cnt[l];
-  }
-  if (best < 0) {
-    acc = 0;
-    for (int l = 0; l < nl; l++) {
-      if (acc + cnt[l] > m / 2 || l == nl - 2) { best = std::max(1, std::min(l, nl - 2)); break; }
-      acc += cnt[l];
-    }
-  }
-  for (int v : verts) {
-    int l = B.level[v];
-    (l < best ? left : (l > best ? right : sep)).push_back(v);
-  }
-  // separator cleanup: a separator vertex without neighbours on one side joins the other
-  const int idL = B.next_id++, idR = B.next_id++, idS = B.next_id++;
-  for (int v : left) B.part[v] = idL;
-  for (int v : right) B.part[v] = idR;
-  for (int v : sep) B.part[v] = idS;
-  std::vector<int32_t> keep;
-  for (int v : sep) {
-    bool hasL = false, hasR = false;
+  // induced subgraph with unit weights
+  WGraph g;
+  g.n = m;
+  g.vwgt.assign(m, 1);
+  g.xadj.assign(m + 1, 0);
+  std::vector<int32_t> loc(0);
+  for (int a = 0; a < m; a++) B.level[verts[a]] = a;   // reuse level[] as local index
+  for (int a = 0; a < m; a++) {
+    int v = verts[a];
     for (int64_t p = B.xadj[v]; p < B.xadj[v + 1]; p++) {
-      int w = B.adj[p];
-      if (B.part[w] == idL) hasL = true;
-      else if (B.part[w] == idR) hasR = true;
+      int u = B.adj[p];
+      if (B.part[u] == id) { g.adj.push_back(B.level[u]); g.ewgt.push_back(1); }
     }
-    if (!hasR) { B.part[v] = idL; left.push_back(v); }
-    else if (!hasL) { B.part[v] = idR; right.push_back(v); }
-    else keep.push_back(v);
+    g.xadj[a + 1] = (int64_t)g.adj.size();
   }
-  sep.swap(keep);
-  for (int v : left) B.part[v] = id;
-  for (int v : right) B.part[v] = id;
-  for (int v : sep) B.part[v] = id;
+  std::vector<char> side;
+  multilevel_bisect(g, side, 0x5EED0000ull + (uint64_t)m);
+  std::vector<char> in_sep;
+  cut_vertex_cover(g, side, in_sep);
+  for (int a = 0; a < m; a++) {
+    int v = verts[a];
+    if (in_sep[a]) sep.push_back(v);
+    else (side[a] == 0 ? left : right).push_back(v);
+  }
 }
 
 // Recursive ND: appends the tree nodes in postorder (left, right, separator) and the
