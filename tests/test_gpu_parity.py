@@ -5,8 +5,7 @@ The kernel updates every column in ascending pivot order with separately rounded
 multiply-subtract and IEEE division, so against the oracle run in that order
 (update_order = ascending) pivots, patterns and values must agree bit for bit.
 Against the oracle's default DFS order the pivots agree at every column whose
-decision margin is not ambiguous (>= 1e-10) and values agree within the
-componentwise rounding bound tol * (|L||U|), tol = max(1e-12, 4 n eps).  Backward error <= 1e-13 and solve residual <= 1e-12 are checked too.
+decision margin is not ambiguous (>= 1e-10) and the patterns are identical.  Backward error <= 1e-13 and solve residual <= 1e-12 are checked too.
 """
 import os
 import sys
@@ -64,13 +63,15 @@ def col_rel_err(p, x, y):
 
 
 def compare_tol(ext, f, n):
-    """GPU (ascending update order) vs the oracle's DFS update order.  Both are the
-    same elimination with the terms of every sum added in a different order, so each
-    entry differs by at most about 2 n eps times the matching entry of |L||U| (the
-    standard componentwise bound for LU): U(j,k) within tol (|L||U|)(j,k), and
-    L(i,k) = x_i / u_kk within tol ((|L||U|)(i,k) + |l_ik| (|L||U|)(k,k)) / |u_kk|.
-    Pivots must agree except at columns whose decision margin is ambiguous."""
-    import scipy.sparse as sp
+    """GPU (ascending update order) vs the oracle's DFS update order: the same
+    elimination with the terms of every sum added in another order.  Pivots must
+    agree except at columns whose decision margin is ambiguous (< 1e-10), and the L
+    and U patterns must then be identical.  Values are not compared entry by entry
+    here: two summation orders differ by forward error, which cancellation can make
+    large in relative terms for tiny entries even when both factorizations are
+    backward stable (seen: 79% in one entry of a 300-row natural-order MNA case with
+    backward error 1e-16 for both).  Values are held to bitwise equality against the
+    oracle in the kernel's own order, and to the backward-error gate."""
     amb = f.margin < 1e-10
     same = np.array_equal(ext.piv, f.piv)
     if not same:
@@ -81,20 +82,6 @@ def compare_tol(ext, f, n):
     np.testing.assert_array_equal(ext.Li, f.Li)
     np.testing.assert_array_equal(ext.Up, f.Up)
     np.testing.assert_array_equal(ext.Ui, f.Ui)
-    tol = max(VAL_TOL, 4.0 * n * np.finfo(float).eps)
-    L = sp.csc_matrix((np.abs(f.Lx), f.Li, f.Lp), shape=(n, n)) + sp.identity(n, format="csc")
-    U = sp.csc_matrix((np.abs(f.Ux), f.Ui, f.Up), shape=(n, n))
-    M = (L @ U).tocsc()
-    M.sort_indices()
-    colL = np.repeat(np.arange(n), np.diff(f.Lp))
-    colU = np.repeat(np.arange(n), np.diff(f.Up))
-    Mu = np.asarray(M[f.Ui, colU]).ravel()
-    assert np.all(np.abs(ext.Ux - f.Ux) <= tol * Mu)
-    ukk = np.abs(f.Ux[f.Up[1:] - 1])
-    Mkk = np.asarray(M[np.arange(n), np.arange(n)]).ravel()
-    Ml = np.asarray(M[f.Li, colL]).ravel()
-    bound = tol * (Ml + np.abs(f.Lx) * Mkk[colL]) / ukk[colL]
-    assert np.all(np.abs(ext.Lx - f.Lx) <= bound)
     return True
 
 
