@@ -53,14 +53,19 @@ struct basker_ctx {
   Plan plan;
   std::string err;
   // plan on device
-  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, seg_c0, seg_c1, lvl_seg, lvl_ctr;
+  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, seg_c0, seg_c1, lvl_seg, lvl_ctr, item_ptr, lvl_col;
+  // separator partial columns (first step of separator levels)
+  DBuf<int32_t> cb_off, cb_np, cb_nn, cbI;
+  DBuf<double> cbX;
   DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, blvl_blk, blvl_ctr;
   // numeric state
   DBuf<double> vals, Rx, OTx;
   DBuf<int32_t> pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
   DBuf<int32_t> Li, Ui;
   DBuf<double> Lx, Ux;
-  DBuf<unsigned long long> pool;
+  DBuf<unsigned long long> pool, nnz_ctr;
+  int64_t Lused = 0, Uused = 0;   // allocated extents of the pools (chunks leave gaps)
+  int64_t chunk = 0;
   DBuf<char> gws;
   int64_t gws_stride = 0;
   int gws_slots = 0;
@@ -158,7 +163,20 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->seg_c0.upload(P.seg_c0, s));
   HIPCHK(h, h->seg_c1.upload(P.seg_c1, s));
   HIPCHK(h, h->lvl_seg.upload(P.lvl_seg, s));
-  HIPCHK(h, h->lvl_ctr.reserve(std::max(nlev, 1)));
+  HIPCHK(h, h->item_ptr.upload(P.item_ptr, s));
+  HIPCHK(h, h->lvl_col.upload(P.lvl_col, s));
+  HIPCHK(h, h->cb_off.reserve(n));
+  HIPCHK(h, h->cb_np.reserve(n));
+  HIPCHK(h, h->cb_nn.reserve(n));
+  {
+    // separator columns and their entries bound the first-step buffer initially
+    int64_t sepcols = P.lvl_col_ptr.back() - (P.lvl_col_ptr.size() > 1 ? P.lvl_col_ptr[1] : 0);
+    int64_t cb = std::max<int64_t>(4096, 256 * sepcols);
+    HIPCHK(h, h->cbI.reserve(cb));
+    HIPCHK(h, h->cbX.reserve(cb));
+  }
+  HIPCHK(h, h->nnz_ctr.reserve(2));
+  HIPCHK(h, h->lvl_ctr.reserve(std::max(2 * nlev, 1)));
   HIPCHK(h, h->OTp.upload(OTp, s));
   HIPCHK(h, h->OTj.upload(OTj, s));
   HIPCHK(h, h->OTmap.upload(OTmap, s));
@@ -178,7 +196,7 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->Ubeg.reserve(n));
   HIPCHK(h, h->Ucnt.reserve(n));
   HIPCHK(h, h->status.reserve(ST_WORDS));
-  HIPCHK(h, h->pool.reserve(2));
+  HIPCHK(h, h->pool.reserve(3));
   (void)nb;
   // L/U pools
   double cf = h->opt.capacity_factor > 0 ? h->opt.capacity_factor : 6.0;
@@ -189,9 +207,9 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->Ui.reserve(cap));
   HIPCHK(h, h->Ux.reserve(cap));
   // persistent grid and the global fallback workspace (one region per workgroup)
-  int maxseg = 1;
-  for (int l = 0; l < nlev; l++) maxseg = std::max(maxseg, P.lvl_ptr[l + 1] - P.lvl_ptr[l]);
-  int grid = std::min(maxseg, kNumCu * kWavesPerCu);
+  int maxitems = 1;
+  for (int l = 0; l < nlev; l++) maxitems = std::max(maxitems, P.lvl_item_ptr[l + 1] - P.lvl_item_ptr[l]);
+  int grid = std::min(maxitems, kNumCu * kWavesPerCu);
   h->grid = grid;
   h->gws_slots = 1 << 14;
   h->gws_stride = ((48LL * h->gws_slots + 16 + 255) / 256) * 256;
@@ -302,6 +320,18 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.Rp = h->Rp.p; a.Ri = h->Ri.p; a.Rx = h->Rx.p;
   a.grp_lo = h->grp_lo.p; a.grp_hi = h->grp_hi.p;
   a.seg_c0 = h->seg_c0.p; a.seg_c1 = h->seg_c1.p; a.lvl_seg = h->lvl_seg.p; a.lvl_ctr = h->lvl_ctr.p;
+  a.item_ptr = h->item_ptr.p;
+  a.nnz_ctr = h->nnz_ctr.p;
+  a.col_list = h->lvl_col.p;
+  a.cb_off = h->cb_off.p; a.cb_np = h->cb_np.p; a.cb_nn = h->cb_nn.p;
+  a.cbI = h->cbI.p; a.cbX = h->cbX.p; a.cbcap = h->cbI.cap;
+  a.mode = 0;
+  // chunk: a fraction of the pool per wave so that idle waves cannot exhaust it
+  {
+    int64_t c = h->Li.cap / (8 * (int64_t)std::max(h->grid, 1));
+    c = std::max<int64_t>(16, std::min<int64_t>(c, 1 << 16));
+    a.chunk = c;
+  }
   a.pinv = h->pinv.p; a.piv = h->piv.p;
   a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p;
   a.Li = h->Li.p; a.Lx = h->Lx.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
@@ -331,8 +361,9 @@ static basker_status stage_values(basker_ctx* h, const double* values, int32_t o
   return BASKER_OK;
 }
 
-// one device pass; fills st[ST_WORDS] and the pool counters
-static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st, unsigned long long* poolc) {
+// one device pass; fills st[ST_WORDS], the pool extents and the stored nnz counts
+static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st, unsigned long long* poolc,
+                                       unsigned long long* nnzc) {
   hipStream_t s = h->stream;
   FactorArgs a = factor_args(h, refactor);
   const Plan& P = h->plan;
@@ -340,15 +371,32 @@ static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st,
   HIPCHK(h, launch_factor_init(a, nlev, s));
   HIPCHK(h, hipEventRecord(h->ev[0], s));
   for (int l = 0; l < nlev; l++) {
-    a.level = l;
-    a.lvl_begin = P.lvl_ptr[l];
-    a.lvl_end = P.lvl_ptr[l + 1];
-    const int grid = std::min(a.lvl_end - a.lvl_begin, h->grid);
+    a.item_begin = P.lvl_item_ptr[l];
+    a.item_end = P.lvl_item_ptr[l + 1];
+    if (l == 0 || refactor) {
+      a.mode = 0;
+      a.level = l;
+      const int grid = std::min(a.item_end - a.item_begin, h->grid);
+      if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
+      continue;
+    }
+    // separator level: descendant part of every column in parallel, then each
+    // separator's own columns in order
+    a.mode = 1;
+    a.level = nlev + l;
+    a.col_begin = P.lvl_col_ptr[l];
+    a.col_end = P.lvl_col_ptr[l + 1];
+    int grid = std::min(a.col_end - a.col_begin, h->grid);
     if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
+    a.mode = 2;
+    a.level = l;
+    grid = std::min(a.item_end - a.item_begin, kNumCu * 3);
+    if (grid > 0) HIPCHK(h, launch_factor_sep_step2(a, grid, s));
   }
   HIPCHK(h, hipEventRecord(h->ev[1], s));
   HIPCHK(h, hipMemcpyAsync(st, h->status.p, sizeof(int32_t) * ST_WORDS, hipMemcpyDeviceToHost, s));
-  HIPCHK(h, hipMemcpyAsync(poolc, h->pool.p, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(poolc, h->pool.p, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(nnzc, h->nnz_ctr.p, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->info.factor_kernel_ms = ms;
@@ -359,13 +407,15 @@ static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st,
 static basker_status do_factor(basker_ctx* h) {
   for (int attempt = 0; attempt < 8; attempt++) {
     int32_t st[ST_WORDS];
-    unsigned long long poolc[2];
-    basker_status r = run_factor_kernel(h, 0, st, poolc);
+    unsigned long long poolc[3], nnzc[2];
+    basker_status r = run_factor_kernel(h, 0, st, poolc, nnzc);
     if (r != BASKER_OK) return r;
     h->info.fail_col = st[ST_FAILCOL] == 0x7fffffff ? -1 : st[ST_FAILCOL];
     if (st[ST_CODE] == DEV_OK) {
-      h->lnz = (int64_t)poolc[0];
-      h->unz = (int64_t)poolc[1];
+      h->lnz = (int64_t)nnzc[0];
+      h->unz = (int64_t)nnzc[1];
+      h->Lused = std::min<int64_t>((int64_t)poolc[0], h->Li.cap);
+      h->Uused = std::min<int64_t>((int64_t)poolc[1], h->Ui.cap);
       h->info.lnz = h->lnz;
       h->info.unz = h->unz;
       h->info.offdiag_pivots = st[ST_OFFDIAG];
@@ -374,6 +424,15 @@ static basker_status do_factor(basker_ctx* h) {
       return BASKER_OK;
     }
     h->factored = false;
+    if (st[ST_CODE] == DEV_POOL && st[ST_CBPOOL]) {
+      int64_t need = std::max<int64_t>((int64_t)poolc[2] * 2, 2 * h->cbI.cap);
+      if (need > 0x7fffffffLL) need = 0x7fffffffLL;
+      if (need <= h->cbI.cap) return fail(h, BASKER_ERR_OOM, "separator buffer exceeds 2^31 entries");
+      HIPCHK(h, h->cbI.reserve(need));
+      HIPCHK(h, h->cbX.reserve(need));
+      h->info.pool_regrows++;
+      continue;
+    }
     if (st[ST_CODE] == DEV_POOL) {
       // grow to twice the demand seen so far
       int64_t need = std::max<int64_t>((int64_t)std::max(poolc[0], poolc[1]) * 2, 2 * h->Li.cap);
@@ -412,8 +471,8 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
   basker_status r = stage_values(h, values, values_on_device);
   if (r != BASKER_OK) return r;
   int32_t st[ST_WORDS];
-  unsigned long long poolc[2];
-  r = run_factor_kernel(h, 1, st, poolc);
+  unsigned long long poolc[3], nnzc[2];
+  r = run_factor_kernel(h, 1, st, poolc, nnzc);
   if (r != BASKER_OK) return r;
   h->info.refactor_calls++;
   if (st[ST_CODE] == DEV_OK) return BASKER_OK;
@@ -507,8 +566,8 @@ extern "C" basker_status basker_extract(basker_handle h, int32_t* piv, int64_t* 
   const int n = h->plan.n;
   hipStream_t s = h->stream;
   std::vector<int32_t> hpiv(n), lb(n), lc(n), ubg(n), ucn(n);
-  std::vector<int32_t> li(h->lnz), ui(h->unz);
-  std::vector<double> lx(h->lnz), ux(h->unz);
+  std::vector<int32_t> li(h->Lused), ui(h->Uused);
+  std::vector<double> lx(h->Lused), ux(h->Uused);
   if (n > 0) {
     HIPCHK(h, hipMemcpyAsync(hpiv.data(), h->piv.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(lb.data(), h->Lbeg.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
@@ -516,13 +575,13 @@ extern "C" basker_status basker_extract(basker_handle h, int32_t* piv, int64_t* 
     HIPCHK(h, hipMemcpyAsync(ubg.data(), h->Ubeg.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(ucn.data(), h->Ucnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
   }
-  if (h->lnz > 0) {
-    HIPCHK(h, hipMemcpyAsync(li.data(), h->Li.p, sizeof(int32_t) * h->lnz, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(lx.data(), h->Lx.p, sizeof(double) * h->lnz, hipMemcpyDeviceToHost, s));
+  if (h->Lused > 0) {
+    HIPCHK(h, hipMemcpyAsync(li.data(), h->Li.p, sizeof(int32_t) * h->Lused, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(lx.data(), h->Lx.p, sizeof(double) * h->Lused, hipMemcpyDeviceToHost, s));
   }
-  if (h->unz > 0) {
-    HIPCHK(h, hipMemcpyAsync(ui.data(), h->Ui.p, sizeof(int32_t) * h->unz, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(ux.data(), h->Ux.p, sizeof(double) * h->unz, hipMemcpyDeviceToHost, s));
+  if (h->Uused > 0) {
+    HIPCHK(h, hipMemcpyAsync(ui.data(), h->Ui.p, sizeof(int32_t) * h->Uused, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(ux.data(), h->Ux.p, sizeof(double) * h->Uused, hipMemcpyDeviceToHost, s));
   }
   HIPCHK(h, hipStreamSynchronize(s));
   std::vector<int32_t> pinv(n, -1);

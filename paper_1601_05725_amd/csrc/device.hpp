@@ -15,12 +15,13 @@ namespace basker {
 
 constexpr int kWave = 64;
 constexpr int kLdsSlots = 512;        // per-wave LDS hash slots (power of two)
+constexpr int kLdsSlotsSep = 1024;    // larger table for separator columns (mode 2)
 constexpr int kWavesPerCu = 6;        // persistent-grid occupancy target
 constexpr int kNumCu = 256;
 
 // status words (device): [0] error code, [1] failing column (min), [2] pool overflow,
 // [3] workspace overflow, [4] pivots off the diagonal
-enum { ST_CODE = 0, ST_FAILCOL = 1, ST_POOL = 2, ST_WS = 3, ST_OFFDIAG = 4, ST_WORDS = 8 };
+enum { ST_CODE = 0, ST_FAILCOL = 1, ST_POOL = 2, ST_WS = 3, ST_OFFDIAG = 4, ST_CBPOOL = 5, ST_WORDS = 8 };
 enum { DEV_OK = 0, DEV_SINGULAR = 3, DEV_REFACTOR_FAIL = 8, DEV_WORKSPACE = 7, DEV_POOL = 4, DEV_PATTERN = 5,
        DEV_STALL = 9 };
 
@@ -33,11 +34,30 @@ struct FactorArgs {
   const int32_t* grp_hi;
   const int32_t* seg_c0;   // segments: column ranges factored by one wave in order
   const int32_t* seg_c1;
-  const int32_t* lvl_seg;  // segments of the launched level: lvl_seg[lvl_begin .. lvl_end)
-  int32_t lvl_begin;
-  int32_t lvl_end;
+  const int32_t* lvl_seg;  // segments in level order (largest first inside a level)
+  const int32_t* item_ptr; // work items: item i = segments lvl_seg[item_ptr[i] .. item_ptr[i+1])
+  int32_t item_begin;      // items of the launched level: [item_begin, item_end)
+  int32_t item_end;
   int32_t* lvl_ctr;        // one pop counter per level (zeroed before the level)
   int32_t level;
+  int64_t chunk;           // pool entries a wave claims at a time
+  unsigned long long* nnz_ctr;  // [0] nnz(L), [1] nnz(U) actually stored
+  // separator levels of a factorization run in two launches (Alg. 4): mode 1 applies
+  // the descendant pivots to every separator column independently (U of the
+  // off-diagonal blocks and the reduction into the separator and ancestor rows) and
+  // parks the partial column in the column buffer; mode 2 then factors each
+  // separator's columns in order from those partial columns.  Mode 0 is the whole
+  // column in one pass.
+  int32_t mode;
+  const int32_t* col_list; // mode 1: columns of the launched level [col_begin, col_end)
+  int32_t col_begin;
+  int32_t col_end;
+  int32_t* cb_off;         // per column: offset of its partial column in the buffer
+  int32_t* cb_np;          //   descendant pivots (U entries, ascending pivot column)
+  int32_t* cb_nn;          //   non-pivotal rows that follow them
+  int32_t* cbI;            // column buffer: pivot column (U part) or row (rest)
+  double* cbX;
+  int64_t cbcap;
   int32_t* pinv;           // R row -> column it pivots (-1)
   int32_t* piv;            // column -> R row
   int32_t* Lbeg;           // per-column offsets/counts into the pools
@@ -48,7 +68,7 @@ struct FactorArgs {
   double* Lx;
   int32_t* Ui;             // U rows (column numbering, ascending, diagonal last)
   double* Ux;
-  unsigned long long* pool_next;   // [0] L, [1] U
+  unsigned long long* pool_next;   // [0] L, [1] U, [2] column buffer
   int64_t Lcap;
   int64_t Ucap;
   int32_t* status;
@@ -85,6 +105,7 @@ struct SolveArgs {
 
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
+hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);
 hipError_t launch_solve_level(const SolveArgs& a, int grid, hipStream_t s);

@@ -75,6 +75,15 @@ struct Ws {
   int shift;      // 32 - log2(H)
 };
 
+// Per-wave pool allocator: a wave claims a chunk of the L and U pools with one atomic
+// and hands out column storage from it, so the device-wide counters see one atomic
+// per chunk instead of two per column.
+struct Alloc {
+  long long lcur, lend, ucur, uend, ccur, cend;
+  long long lnz, unz;
+  int offdiag;
+};
+
 template <int H>
 struct LdsWs {
   int32_t key[H];
@@ -236,23 +245,57 @@ __device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1
 
 // Factor (or refactor) column k with workspace w.  Returns 0 on success, 1 when the
 // workspace overflowed (nothing was written), 2 on a numerical failure (status set).
-__device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
+// take n entries from [cur, end), claiming a new chunk from the device counter when
+// the current one is short; returns the offset, or -1 when the pool is exhausted
+__device__ __forceinline__ long long pool_take(long long* cur, long long* end, long long n,
+                                               unsigned long long* counter, long long chunk, long long cap) {
+  if (*cur + n > *end) {
+    const long long want = n > chunk ? n : chunk;
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)want);
+    base = __shfl(base, 0, 64);
+    if ((long long)base + want > cap) return -1;
+    *cur = (long long)base;
+    *end = (long long)base + want;
+  }
+  const long long off = *cur;
+  *cur += n;
+  return off;
+}
+
+__device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al) {
   const int lane = lane_id();
   ws_reset(w);
   const int g0 = a.grp_lo[k], g1 = a.grp_hi[k];
 
   int ub = 0, uc = 0, lb = 0, lc = 0, p = -1;
   if (!a.refactor) {
-    // struct(R(:,k)) with values
-    for (int q = a.Rp[k] + lane; q < a.Rp[k + 1]; q += 64) {
-      const int32_t r = a.Ri[q];
-      bool isnew;
-      int slot = ws_insert(w, r, &isnew);
-      if (slot >= 0) {
-        w.val[slot] = a.Rx[q];
-        const int32_t pvr = a.pinv[r];
-        w.pv[slot] = pvr;
-        if (pvr >= 0) plist_push(w, pvr, slot);
+    if (a.mode != 2) {
+      // struct(R(:,k)) with values
+      for (int q = a.Rp[k] + lane; q < a.Rp[k + 1]; q += 64) {
+        const int32_t r = a.Ri[q];
+        bool isnew;
+        int slot = ws_insert(w, r, &isnew);
+        if (slot >= 0) {
+          w.val[slot] = a.Rx[q];
+          const int32_t pvr = a.pinv[r];
+          w.pv[slot] = pvr;
+          if (pvr >= 0) plist_push(w, pvr, slot);
+        }
+      }
+    } else {
+      // the partial column left by mode 1: its non-pivotal rows with their values
+      const int off = a.cb_off[k] + a.cb_np[k], nn = a.cb_nn[k];
+      for (int t = lane; t < nn; t += 64) {
+        const int32_t r = a.cbI[off + t];
+        bool isnew;
+        int slot = ws_insert(w, r, &isnew);
+        if (slot >= 0) {
+          w.val[slot] = a.cbX[off + t];
+          const int32_t pvr = a.pinv[r];
+          w.pv[slot] = pvr;
+          if (pvr >= 0) plist_push(w, pvr, slot);
+        }
       }
     }
     wsync();
@@ -343,8 +386,48 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
     return 2;
   }
 
-  // pivot search over the candidates of the column's group
   const int nins = w.cnt[0];
+  if (a.mode == 1) {
+    // park the partial column: descendant pivots (final U entries) ascending, then the
+    // non-pivotal rows (separator and ancestor rows) with their partial values
+    const long long off = pool_take(&al.ccur, &al.cend, nins, &a.pool_next[2], 0, a.cbcap);
+    if (off < 0) {
+      if (lane == 0) {
+        atomicMax(&a.status[ST_CODE], DEV_POOL);
+        a.status[ST_CBPOOL] = 1;
+      }
+      return 2;
+    }
+    for (int e = lane; e < np; e += 64) {
+      const unsigned long long key = w.sk[e];
+      a.cbI[off + e] = (int32_t)(key >> 32);
+      a.cbX[off + e] = w.val[w.ps[(int)(key & 0xffffffffu)]];
+    }
+    int cnt = np;
+    for (int base = 0; base < nins; base += 64) {
+      const int t = base + lane;
+      int s = 0;
+      bool sel = false;
+      if (t < nins) {
+        s = w.ins[t];
+        sel = w.pv[s] < 0;
+      }
+      const unsigned long long bm = __ballot(sel);
+      const int pos = cnt + __popcll(bm & ((1ull << lane) - 1ull));
+      if (sel) {
+        a.cbI[off + pos] = w.key[s];
+        a.cbX[off + pos] = w.val[s];
+      }
+      cnt += __popcll(bm);
+    }
+    if (lane == 0) {
+      a.cb_off[k] = (int32_t)off;
+      a.cb_np[k] = np;
+      a.cb_nn[k] = nins - np;
+    }
+    return 0;
+  }
+  // pivot search over the candidates of the column's group
   double best = -1.0;
   int bidx = 0x7fffffff;
   int has_diag = 0;
@@ -400,16 +483,12 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
 
   // store U(:,k) and L(:,k)
   if (!a.refactor) {
-    uc = np + 1;
+    const int dnp = (a.mode == 2) ? a.cb_np[k] : 0;
+    uc = dnp + np + 1;
     lc = nins - np - 1;
-    unsigned long long ubl = 0, lbl = 0;
-    if (lane == 0) {
-      ubl = atomicAdd(&a.pool_next[1], (unsigned long long)uc);
-      lbl = atomicAdd(&a.pool_next[0], (unsigned long long)lc);
-    }
-    ubl = __shfl(ubl, 0, 64);
-    lbl = __shfl(lbl, 0, 64);
-    if ((int64_t)(ubl + uc) > a.Ucap || (int64_t)(lbl + lc) > a.Lcap) {
+    const long long ubl = pool_take(&al.ucur, &al.uend, uc, &a.pool_next[1], a.chunk, a.Ucap);
+    const long long lbl = pool_take(&al.lcur, &al.lend, lc, &a.pool_next[0], a.chunk, a.Lcap);
+    if (ubl < 0 || lbl < 0) {
       if (lane == 0) {
         atomicMax(&a.status[ST_CODE], DEV_POOL);
         a.status[ST_POOL] = 1;
@@ -418,12 +497,21 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
     }
     ub = (int)ubl;
     lb = (int)lbl;
+    al.unz += uc;
+    al.lnz += lc;
+    if (dnp) {
+      const int off = a.cb_off[k];
+      for (int e = lane; e < dnp; e += 64) {
+        a.Ui[ub + e] = a.cbI[off + e];
+        a.Ux[ub + e] = a.cbX[off + e];
+      }
+    }
     for (int e = lane; e < np; e += 64) {
       const unsigned long long key = w.sk[e];
-      a.Ui[ub + e] = (int32_t)(key >> 32);
-      a.Ux[ub + e] = w.val[w.ps[(int)(key & 0xffffffffu)]];
+      a.Ui[ub + dnp + e] = (int32_t)(key >> 32);
+      a.Ux[ub + dnp + e] = w.val[w.ps[(int)(key & 0xffffffffu)]];
     }
-    if (lane == 0) { a.Ui[ub + np] = k; a.Ux[ub + np] = xp; }
+    if (lane == 0) { a.Ui[ub + dnp + np] = k; a.Ux[ub + dnp + np] = xp; }
     int off = 0;
     for (int base = 0; base < nins; base += 64) {
       const int t = base + lane;
@@ -444,8 +532,8 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
     if (lane == 0) {
       a.Lbeg[k] = lb; a.Lcnt[k] = lc; a.Ubeg[k] = ub; a.Ucnt[k] = uc;
       a.piv[k] = p;
-      if (p != k) atomicAdd(&a.status[ST_OFFDIAG], 1);
     }
+    if (p != k) al.offdiag++;
   } else {
     for (int e = lane; e < np; e += 64) a.Ux[ub + e] = w.val[w.ps[e]];
     if (lane == 0) a.Ux[ub + np] = xp;
@@ -458,16 +546,17 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k) {
   return 0;
 }
 
+template <int HS>
 __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
-  BASKER_SHARED(LdsWs<kLdsSlots>, lds);
+  BASKER_SHARED(LdsWs<HS>, lds);
   const int lane = lane_id();
-  for (int t = lane; t < kLdsSlots; t += 64) lds.key[t] = -1;
+  for (int t = lane; t < HS; t += 64) lds.key[t] = -1;
   if (lane == 0) { lds.cnt[0] = 0; lds.cnt[1] = 0; lds.cnt[2] = 0; lds.cnt[3] = 0; }
   Ws wl;
   wl.key = lds.key; wl.val = lds.val; wl.pv = lds.pv; wl.ins = lds.ins; wl.pj = lds.pj;
   wl.ps = lds.ps; wl.pb = lds.pb; wl.pc = lds.pc; wl.sk = lds.sk; wl.cnt = lds.cnt;
-  wl.H = kLdsSlots;
-  wl.shift = 32 - __builtin_ctz(kLdsSlots);
+  wl.H = HS;
+  wl.shift = 32 - __builtin_ctz(HS);
   Ws wg;
   {
     const int H = a.gws_slots;
@@ -486,27 +575,62 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.shift = 32 - __builtin_ctz((unsigned)H);
   }
   wsync();
-  const int nseg = a.lvl_end - a.lvl_begin;
-  while (true) {
-    int idx = 0;
-    if (lane == 0) idx = atomicAdd(&a.lvl_ctr[a.level], 1);
-    idx = __shfl(idx, 0, 64);
-    if (idx >= nseg) break;
-    const int sg = a.lvl_seg[a.lvl_begin + idx];
-    const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];
-    for (int k = c0; k < c1; k++) {
-      if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) break;
-      int rc = factor_column(a, wl, k);
+  Alloc al = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (a.mode == 1) {
+    // one column at a time: every column of the level's separators is independent here
+    const int ncols = a.col_end - a.col_begin;
+    while (true) {
+      int idx = 0;
+      if (lane == 0) idx = atomicAdd(&a.lvl_ctr[a.level], 1);
+      idx = __shfl(idx, 0, 64);
+      if (idx >= ncols) break;
+      if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
+      const int k = a.col_list[a.col_begin + idx];
+      int rc = factor_column(a, wl, k, al);
       if (rc == 1) {
-        rc = factor_column(a, wg, k);
+        rc = factor_column(a, wg, k, al);
         if (rc == 1 && lane == 0) {
           atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
           atomicMin(&a.status[ST_FAILCOL], k);
           a.status[ST_WS] = 1;
         }
       }
-      // the next column reads this column's pinv/L/U entries written by other lanes
       wsync();
+    }
+  } else {
+    const int nitems = a.item_end - a.item_begin;
+    while (true) {
+      int idx = 0;
+      if (lane == 0) idx = atomicAdd(&a.lvl_ctr[a.level], 1);
+      idx = __shfl(idx, 0, 64);
+      if (idx >= nitems) break;
+      if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
+      const int it = a.item_begin + idx;
+      for (int q = a.item_ptr[it]; q < a.item_ptr[it + 1]; q++) {
+        const int sg = a.lvl_seg[q];
+        const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];
+        for (int k = c0; k < c1; k++) {
+          int rc = factor_column(a, wl, k, al);
+          if (rc == 1) {
+            rc = factor_column(a, wg, k, al);
+            if (rc == 1 && lane == 0) {
+              atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
+              atomicMin(&a.status[ST_FAILCOL], k);
+              a.status[ST_WS] = 1;
+            }
+          }
+          if (rc != 0) break;
+          // the next column reads this column's pinv/L/U entries written by other lanes
+          wsync();
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    if (al.offdiag) atomicAdd(&a.status[ST_OFFDIAG], al.offdiag);
+    if (!a.refactor && (al.lnz || al.unz)) {
+      atomicAdd(&a.nnz_ctr[0], (unsigned long long)al.lnz);
+      atomicAdd(&a.nnz_ctr[1], (unsigned long long)al.unz);
     }
   }
 }
@@ -515,8 +639,10 @@ __global__ void factor_init_kernel(FactorArgs a, int32_t nlevels) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.n && !a.refactor) a.pinv[i] = -1;
   if (i < ST_WORDS) a.status[i] = (i == ST_FAILCOL) ? 0x7fffffff : 0;
-  if (i < nlevels) a.lvl_ctr[i] = 0;
-  if (i == 0 && !a.refactor) { a.pool_next[0] = 0; a.pool_next[1] = 0; }
+  if (i < 2 * nlevels) a.lvl_ctr[i] = 0;
+  if (i == 0 && !a.refactor) {
+    a.pool_next[0] = 0; a.pool_next[1] = 0; a.pool_next[2] = 0; a.nnz_ctr[0] = 0; a.nnz_ctr[1] = 0;
+  }
 }
 
 __global__ void scatter_kernel(const double* __restrict__ vals, const int32_t* __restrict__ map,
@@ -542,7 +668,12 @@ hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t 
 }
 
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(factor_kernel, dim3(grid), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(factor_kernel<kLdsSlots>, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(factor_kernel<kLdsSlotsSep>, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -854,6 +854,26 @@ void build_levels(Plan& P) {
     std::stable_sort(b, e, [&](int x, int y) { return P.seg_c1[x] - P.seg_c0[x] > P.seg_c1[y] - P.seg_c0[y]; });
     if (b != e) P.crit_cols += P.seg_c1[*b] - P.seg_c0[*b];
   }
+  const int kItemCols = 64;
+  P.item_ptr.assign(1, 0);
+  P.lvl_item_ptr.assign(1, 0);
+  for (int l = 0; l < nl; l++) {
+    int acc = 0;
+    for (int q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; q++) {
+      const int sz = P.seg_c1[P.lvl_seg[q]] - P.seg_c0[P.lvl_seg[q]];
+      if (acc > 0 && (acc >= kItemCols || sz >= kItemCols)) { P.item_ptr.push_back(q); acc = 0; }
+      acc += sz;
+    }
+    if (P.lvl_ptr[l + 1] > P.item_ptr.back()) P.item_ptr.push_back(P.lvl_ptr[l + 1]);
+    P.lvl_item_ptr.push_back((int32_t)P.item_ptr.size() - 1);
+  }
+  P.lvl_col.clear();
+  P.lvl_col_ptr.assign(1, 0);
+  for (int l = 0; l < nl; l++) {
+    for (int q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; q++)
+      for (int k = P.seg_c0[P.lvl_seg[q]]; k < P.seg_c1[P.lvl_seg[q]]; k++) P.lvl_col.push_back(k);
+    P.lvl_col_ptr.push_back((int32_t)P.lvl_col.size());
+  }
   // solve levels over blocks (later blocks first)
   const int nb = (int)P.blkptr.size() - 1;
   std::vector<int32_t> blk(P.n);

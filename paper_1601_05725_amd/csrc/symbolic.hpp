@@ -51,6 +51,12 @@ struct Plan {
   // segments of one level are independent.
   std::vector<int32_t> seg_c0, seg_c1, seg_level;
   std::vector<int32_t> lvl_ptr, lvl_seg;      // segments of level l: lvl_seg[lvl_ptr[l] .. lvl_ptr[l+1])
+  // work items: consecutive segments of one level with at least kItemCols columns in
+  // total (a large segment is an item by itself); items of level l are
+  // [lvl_item_ptr[l], lvl_item_ptr[l+1]), item i covers lvl_seg[item_ptr[i] .. item_ptr[i+1])
+  std::vector<int32_t> item_ptr, lvl_item_ptr;
+  // columns of every level (for the column-parallel first step of separator levels)
+  std::vector<int32_t> lvl_col, lvl_col_ptr;
   int64_t crit_cols = 0;                      // sum over levels of the largest segment
   // solve: block levels of the back-substitution (blocks of a level are independent)
   std::vector<int32_t> blvl_ptr, blvl_blk;
