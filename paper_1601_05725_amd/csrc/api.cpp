@@ -53,10 +53,15 @@ struct basker_ctx {
   Plan plan;
   std::string err;
   // plan on device
-  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, seg_c0, seg_c1, lvl_seg, lvl_ctr, item_ptr, lvl_col;
+  DBuf<int32_t> Rp, Ri, Rmap, grp_lo, grp_hi, seg_c0, seg_c1, lvl_seg, lvl_ctr, item_lo, item_hi, lvl_col;
   // separator partial columns (first step of separator levels)
   DBuf<int32_t> cb_off, cb_np, cb_nn, cbI;
   DBuf<double> cbX;
+  // dense separator panels
+  DBuf<int32_t> dsep_seg, dsep_H, dsep_rng_ptr, dsep_rng_g0, dsep_rng_len, dsep_rng_loc, piv_local;
+  DBuf<int64_t> dsep_poff, dsep_soff;
+  DBuf<double> dpanel;
+  DBuf<unsigned long long> dbits;
   DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, blvl_blk, blvl_ctr;
   // numeric state
   DBuf<double> vals, Rx, OTx;
@@ -163,8 +168,20 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->seg_c0.upload(P.seg_c0, s));
   HIPCHK(h, h->seg_c1.upload(P.seg_c1, s));
   HIPCHK(h, h->lvl_seg.upload(P.lvl_seg, s));
-  HIPCHK(h, h->item_ptr.upload(P.item_ptr, s));
+  HIPCHK(h, h->item_lo.upload(P.item_lo, s));
+  HIPCHK(h, h->item_hi.upload(P.item_hi, s));
   HIPCHK(h, h->lvl_col.upload(P.lvl_col, s));
+  HIPCHK(h, h->dsep_seg.upload(P.dsep_seg, s));
+  HIPCHK(h, h->dsep_H.upload(P.dsep_H, s));
+  HIPCHK(h, h->dsep_rng_ptr.upload(P.dsep_rng_ptr, s));
+  HIPCHK(h, h->dsep_rng_g0.upload(P.dsep_rng_g0, s));
+  HIPCHK(h, h->dsep_rng_len.upload(P.dsep_rng_len, s));
+  HIPCHK(h, h->dsep_rng_loc.upload(P.dsep_rng_loc, s));
+  HIPCHK(h, h->dsep_poff.upload(P.dsep_poff, s));
+  HIPCHK(h, h->dsep_soff.upload(P.dsep_soff, s));
+  HIPCHK(h, h->dpanel.reserve(std::max<int64_t>(P.dsep_panel_total, 1)));
+  HIPCHK(h, h->dbits.reserve(std::max<int64_t>(P.dsep_bits_total, 1)));
+  HIPCHK(h, h->piv_local.reserve(n));
   HIPCHK(h, h->cb_off.reserve(n));
   HIPCHK(h, h->cb_np.reserve(n));
   HIPCHK(h, h->cb_nn.reserve(n));
@@ -320,7 +337,8 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.Rp = h->Rp.p; a.Ri = h->Ri.p; a.Rx = h->Rx.p;
   a.grp_lo = h->grp_lo.p; a.grp_hi = h->grp_hi.p;
   a.seg_c0 = h->seg_c0.p; a.seg_c1 = h->seg_c1.p; a.lvl_seg = h->lvl_seg.p; a.lvl_ctr = h->lvl_ctr.p;
-  a.item_ptr = h->item_ptr.p;
+  a.item_lo = h->item_lo.p;
+  a.item_hi = h->item_hi.p;
   a.nnz_ctr = h->nnz_ctr.p;
   a.col_list = h->lvl_col.p;
   a.cb_off = h->cb_off.p; a.cb_np = h->cb_np.p; a.cb_nn = h->cb_nn.p;
@@ -370,28 +388,49 @@ static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st,
   const int nlev = (int)P.lvl_ptr.size() - 1;
   HIPCHK(h, launch_factor_init(a, nlev, s));
   HIPCHK(h, hipEventRecord(h->ev[0], s));
+  DenseSepArgs dA{};
+  dA.dsep_seg = h->dsep_seg.p; dA.seg_c0 = h->seg_c0.p; dA.seg_c1 = h->seg_c1.p; dA.dsep_H = h->dsep_H.p;
+  dA.rng_ptr = h->dsep_rng_ptr.p; dA.rng_g0 = h->dsep_rng_g0.p; dA.rng_len = h->dsep_rng_len.p;
+  dA.rng_loc = h->dsep_rng_loc.p; dA.poff = h->dsep_poff.p; dA.soff = h->dsep_soff.p;
+  dA.panel = h->dpanel.p; dA.bits = h->dbits.p; dA.piv_local = h->piv_local.p;
+  dA.cb_off = h->cb_off.p; dA.cb_np = h->cb_np.p; dA.cb_nn = h->cb_nn.p; dA.cbI = h->cbI.p; dA.cbX = h->cbX.p;
+  dA.pinv = h->pinv.p; dA.piv = h->piv.p;
+  dA.Lbeg = h->Lbeg.p; dA.Lcnt = h->Lcnt.p; dA.Ubeg = h->Ubeg.p; dA.Ucnt = h->Ucnt.p;
+  dA.Li = h->Li.p; dA.Lx = h->Lx.p; dA.Ui = h->Ui.p; dA.Ux = h->Ux.p;
+  dA.pool_next = h->pool.p; dA.Lcap = h->Li.cap; dA.Ucap = h->Ui.cap; dA.nnz_ctr = h->nnz_ctr.p;
+  dA.status = h->status.p; dA.tau = h->opt.pivot_tol; dA.diag_pref = h->opt.diag_pref; dA.refactor = refactor;
   for (int l = 0; l < nlev; l++) {
     a.item_begin = P.lvl_item_ptr[l];
     a.item_end = P.lvl_item_ptr[l + 1];
-    if (l == 0 || refactor) {
+    if (l == 0) {
       a.mode = 0;
       a.level = l;
       const int grid = std::min(a.item_end - a.item_begin, h->grid);
       if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
       continue;
     }
-    // separator level: descendant part of every column in parallel, then each
-    // separator's own columns in order
+    // separator level (Alg. 4): the descendant part of every separator column in
+    // parallel, then each separator's own columns -- sparse and in order for small
+    // separators, on a dense panel for the others
     a.mode = 1;
     a.level = nlev + l;
     a.col_begin = P.lvl_col_ptr[l];
-    a.col_end = P.lvl_col_ptr[l + 1];
+    a.col_end = refactor ? P.lvl_col_ptr[l] + P.lvl_dcol_cnt[l] : P.lvl_col_ptr[l + 1];
     int grid = std::min(a.col_end - a.col_begin, h->grid);
     if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
-    a.mode = 2;
     a.level = l;
     grid = std::min(a.item_end - a.item_begin, kNumCu * 3);
-    if (grid > 0) HIPCHK(h, launch_factor_sep_step2(a, grid, s));
+    if (grid > 0) {
+      if (refactor) {
+        a.mode = 0;
+        HIPCHK(h, launch_factor_level(a, std::min(grid, h->grid), s));
+      } else {
+        a.mode = 2;
+        HIPCHK(h, launch_factor_sep_step2(a, grid, s));
+      }
+    }
+    dA.d_begin = P.lvl_dsep_ptr[l];
+    HIPCHK(h, launch_sepdense(dA, P.lvl_dsep_ptr[l + 1] - P.lvl_dsep_ptr[l], s));
   }
   HIPCHK(h, hipEventRecord(h->ev[1], s));
   HIPCHK(h, hipMemcpyAsync(st, h->status.p, sizeof(int32_t) * ST_WORDS, hipMemcpyDeviceToHost, s));

@@ -35,7 +35,8 @@ struct FactorArgs {
   const int32_t* seg_c0;   // segments: column ranges factored by one wave in order
   const int32_t* seg_c1;
   const int32_t* lvl_seg;  // segments in level order (largest first inside a level)
-  const int32_t* item_ptr; // work items: item i = segments lvl_seg[item_ptr[i] .. item_ptr[i+1])
+  const int32_t* item_lo;  // work items: item i = segments lvl_seg[item_lo[i] .. item_hi[i])
+  const int32_t* item_hi;
   int32_t item_begin;      // items of the launched level: [item_begin, item_end)
   int32_t item_end;
   int32_t* lvl_ctr;        // one pop counter per level (zeroed before the level)
@@ -103,6 +104,40 @@ struct SolveArgs {
   double* Z;               // n x nrhs scratch: solution in R-column numbering
 };
 
+struct DenseSepArgs {
+  const int32_t* dsep_seg;  // dense separators: segment, panel rows, row ranges, offsets
+  const int32_t* seg_c0;
+  const int32_t* seg_c1;
+  const int32_t* dsep_H;
+  const int32_t* rng_ptr;
+  const int32_t* rng_g0;
+  const int32_t* rng_len;
+  const int32_t* rng_loc;
+  const int64_t* poff;
+  const int64_t* soff;
+  int32_t d_begin;          // separators of the launched level: [d_begin, d_begin + grid)
+  double* panel;
+  unsigned long long* bits;
+  int32_t* piv_local;       // per column: local pivot row inside its separator panel
+  const int32_t* cb_off;    // partial columns from the first step
+  const int32_t* cb_np;
+  const int32_t* cb_nn;
+  const int32_t* cbI;
+  const double* cbX;
+  int32_t* pinv;
+  int32_t* piv;
+  int32_t* Lbeg; int32_t* Lcnt; int32_t* Ubeg; int32_t* Ucnt;
+  int32_t* Li; double* Lx; int32_t* Ui; double* Ux;
+  unsigned long long* pool_next;
+  int64_t Lcap, Ucap;
+  unsigned long long* nnz_ctr;
+  int32_t* status;
+  double tau;
+  int32_t diag_pref;
+  int32_t refactor;
+};
+
+hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s);
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);

@@ -269,7 +269,7 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
   const int g0 = a.grp_lo[k], g1 = a.grp_hi[k];
 
   int ub = 0, uc = 0, lb = 0, lc = 0, p = -1;
-  if (!a.refactor) {
+  if (!a.refactor || a.mode == 1) {
     if (a.mode != 2) {
       // struct(R(:,k)) with values
       for (int q = a.Rp[k] + lane; q < a.Rp[k + 1]; q += 64) {
@@ -354,7 +354,7 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
 
   // topological order: ascending pivot column
   const int np = w.cnt[1];
-  if (!a.refactor) {
+  if (!a.refactor || a.mode == 1) {
     plist_sort(w, np);
   } else {
     for (int t = lane; t < np; t += 64) w.sk[t] = ((unsigned long long)(unsigned)w.pj[t] << 32) | (unsigned)t;
@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
       if (idx >= nitems) break;
       if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
       const int it = a.item_begin + idx;
-      for (int q = a.item_ptr[it]; q < a.item_ptr[it + 1]; q++) {
+      for (int q = a.item_lo[it]; q < a.item_hi[it]; q++) {
         const int sg = a.lvl_seg[q];
         const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];
         for (int k = c0; k < c1; k++) {

@@ -838,8 +838,18 @@ void finish_schedule(Plan& P) {
 // off-diagonal entries touch, so level(b) = 1 + max level of those blocks.
 void build_levels(Plan& P) {
   const int ns = (int)P.seg_c0.size();
+  const int kDenseSepMin = 16;
   int nl = 0;
   for (int s = 0; s < ns; s++) nl = std::max(nl, P.seg_level[s] + 1);
+  // dense separators: level >= 1 segments of at least kDenseSepMin columns
+  std::vector<char> dense(ns, 0);
+  for (int s = 0; s < ns; s++) {
+    if (P.seg_level[s] < 1 || P.seg_c1[s] - P.seg_c0[s] < kDenseSepMin || P.seg_grp.empty() || P.seg_grp[s] < 0)
+      continue;
+    int64_t H = 0;
+    for (int g = P.seg_grp[s]; g >= 0; g = P.grp_parent[g]) H += P.grpptr[g + 1] - P.grpptr[g];
+    if (H <= 16384) dense[s] = 1;   // panel rows fit the kernel's row bitmaps
+  }
   P.lvl_ptr.assign(nl + 1, 0);
   for (int s = 0; s < ns; s++) P.lvl_ptr[P.seg_level[s] + 1]++;
   for (int l = 0; l < nl; l++) P.lvl_ptr[l + 1] += P.lvl_ptr[l];
@@ -851,28 +861,77 @@ void build_levels(Plan& P) {
   P.crit_cols = 0;
   for (int l = 0; l < nl; l++) {
     auto b = P.lvl_seg.begin() + P.lvl_ptr[l], e = P.lvl_seg.begin() + P.lvl_ptr[l + 1];
-    std::stable_sort(b, e, [&](int x, int y) { return P.seg_c1[x] - P.seg_c0[x] > P.seg_c1[y] - P.seg_c0[y]; });
-    if (b != e) P.crit_cols += P.seg_c1[*b] - P.seg_c0[*b];
+    // dense separators first, then largest first
+    std::stable_sort(b, e, [&](int x, int y) {
+      if (dense[x] != dense[y]) return dense[x] > dense[y];
+      return P.seg_c1[x] - P.seg_c0[x] > P.seg_c1[y] - P.seg_c0[y];
+    });
+    int mx = 0;
+    for (auto it = b; it != e; ++it) mx = std::max(mx, P.seg_c1[*it] - P.seg_c0[*it]);
+    P.crit_cols += mx;
   }
+  // work items over the non-dense segments of every level: item i covers
+  // lvl_seg[item_lo[i] .. item_hi[i])
   const int kItemCols = 64;
-  P.item_ptr.assign(1, 0);
+  P.item_lo.clear();
+  P.item_hi.clear();
   P.lvl_item_ptr.assign(1, 0);
   for (int l = 0; l < nl; l++) {
-    int acc = 0;
-    for (int q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; q++) {
+    int q0 = P.lvl_ptr[l];
+    while (q0 < P.lvl_ptr[l + 1] && dense[P.lvl_seg[q0]]) q0++;
+    int start = q0, acc = 0;
+    for (int q = q0; q < P.lvl_ptr[l + 1]; q++) {
       const int sz = P.seg_c1[P.lvl_seg[q]] - P.seg_c0[P.lvl_seg[q]];
-      if (acc > 0 && (acc >= kItemCols || sz >= kItemCols)) { P.item_ptr.push_back(q); acc = 0; }
+      if (acc > 0 && (acc >= kItemCols || sz >= kItemCols)) {
+        P.item_lo.push_back(start); P.item_hi.push_back(q);
+        start = q;
+        acc = 0;
+      }
       acc += sz;
     }
-    if (P.lvl_ptr[l + 1] > P.item_ptr.back()) P.item_ptr.push_back(P.lvl_ptr[l + 1]);
-    P.lvl_item_ptr.push_back((int32_t)P.item_ptr.size() - 1);
+    if (P.lvl_ptr[l + 1] > start) { P.item_lo.push_back(start); P.item_hi.push_back(P.lvl_ptr[l + 1]); }
+    P.lvl_item_ptr.push_back((int32_t)P.item_lo.size());
   }
+  // columns per level, dense separators' columns first
   P.lvl_col.clear();
   P.lvl_col_ptr.assign(1, 0);
+  P.lvl_dcol_cnt.assign(nl, 0);
   for (int l = 0; l < nl; l++) {
-    for (int q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; q++)
-      for (int k = P.seg_c0[P.lvl_seg[q]]; k < P.seg_c1[P.lvl_seg[q]]; k++) P.lvl_col.push_back(k);
+    for (int q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; q++) {
+      const int sg = P.lvl_seg[q];
+      if (dense[sg]) P.lvl_dcol_cnt[l] += P.seg_c1[sg] - P.seg_c0[sg];
+      for (int k = P.seg_c0[sg]; k < P.seg_c1[sg]; k++) P.lvl_col.push_back(k);
+    }
     P.lvl_col_ptr.push_back((int32_t)P.lvl_col.size());
+  }
+  // dense separator panels: own rows, then each ancestor separator's rows
+  P.dsep_seg.clear(); P.dsep_H.clear(); P.dsep_rng_g0.clear(); P.dsep_rng_len.clear(); P.dsep_rng_loc.clear();
+  P.dsep_rng_ptr.assign(1, 0);
+  P.dsep_poff.clear(); P.dsep_soff.clear();
+  P.lvl_dsep_ptr.assign(1, 0);
+  P.dsep_panel_total = 0;
+  P.dsep_bits_total = 0;
+  for (int l = 0; l < nl; l++) {
+    for (int q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; q++) {
+      const int sg = P.lvl_seg[q];
+      if (!dense[sg]) continue;
+      const int m = P.seg_c1[sg] - P.seg_c0[sg];
+      int H = 0;
+      for (int g = P.seg_grp.empty() ? -1 : P.seg_grp[sg]; g >= 0; g = P.grp_parent.empty() ? -1 : P.grp_parent[g]) {
+        P.dsep_rng_g0.push_back(P.grpptr[g]);
+        P.dsep_rng_len.push_back(P.grpptr[g + 1] - P.grpptr[g]);
+        P.dsep_rng_loc.push_back(H);
+        H += P.grpptr[g + 1] - P.grpptr[g];
+      }
+      P.dsep_rng_ptr.push_back((int32_t)P.dsep_rng_g0.size());
+      P.dsep_seg.push_back(sg);
+      P.dsep_H.push_back(H);
+      P.dsep_poff.push_back(P.dsep_panel_total);
+      P.dsep_soff.push_back(P.dsep_bits_total);
+      P.dsep_panel_total += (int64_t)H * m;
+      P.dsep_bits_total += (int64_t)((H + 63) / 64) * m;
+    }
+    P.lvl_dsep_ptr.push_back((int32_t)P.dsep_seg.size());
   }
   // solve levels over blocks (later blocks first)
   const int nb = (int)P.blkptr.size() - 1;
@@ -1068,6 +1127,9 @@ int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
   }
   // segments and levels
   {
+    auto group_of = [&](int col) {
+      return (int32_t)(std::upper_bound(P.grpptr.begin(), P.grpptr.end(), col) - P.grpptr.begin() - 1);
+    };
     std::vector<int32_t> seg_of_block_level;  // level per segment
     std::vector<char> is_nd_b(P.blkptr.size(), 0);
     std::vector<const NdBlockInfo*> info_of(P.blkptr.size(), nullptr);
@@ -1085,6 +1147,8 @@ int build_plan(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax,
         c += info.node_size[t];
       }
     }
+    P.seg_grp.resize(P.seg_c0.size());
+    for (size_t sg = 0; sg < P.seg_c0.size(); sg++) P.seg_grp[sg] = group_of(P.seg_c0[sg]);
   }
   build_levels(P);
   return 0;
@@ -1133,6 +1197,7 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
   for (int b = 0; b < nblk; b++) {
     P.seg_c0.push_back(P.blkptr[b]); P.seg_c1.push_back(P.blkptr[b + 1]); P.seg_level.push_back(0);
   }
+  P.seg_grp.assign(P.seg_c0.size(), -1);
   build_levels(P);
   return 0;
 }

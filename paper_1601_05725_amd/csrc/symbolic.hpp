@@ -53,10 +53,18 @@ struct Plan {
   std::vector<int32_t> lvl_ptr, lvl_seg;      // segments of level l: lvl_seg[lvl_ptr[l] .. lvl_ptr[l+1])
   // work items: consecutive segments of one level with at least kItemCols columns in
   // total (a large segment is an item by itself); items of level l are
-  // [lvl_item_ptr[l], lvl_item_ptr[l+1]), item i covers lvl_seg[item_ptr[i] .. item_ptr[i+1])
-  std::vector<int32_t> item_ptr, lvl_item_ptr;
-  // columns of every level (for the column-parallel first step of separator levels)
-  std::vector<int32_t> lvl_col, lvl_col_ptr;
+  // [lvl_item_ptr[l], lvl_item_ptr[l+1]), item i covers lvl_seg[item_lo[i] .. item_hi[i])
+  std::vector<int32_t> item_lo, item_hi, lvl_item_ptr;
+  // columns of every level (for the column-parallel first step of separator levels);
+  // in a level the columns of dense separators come first (lvl_dcol_cnt of them)
+  std::vector<int32_t> lvl_col, lvl_col_ptr, lvl_dcol_cnt;
+  // dense separators: ND separators of at least kDenseSepMin columns are factored
+  // right-looking on a dense panel whose rows are the separator's own rows followed by
+  // the rows of its ancestor separators (the only rows its columns can reach)
+  std::vector<int32_t> dsep_seg, dsep_H, dsep_rng_ptr, dsep_rng_g0, dsep_rng_len, dsep_rng_loc, lvl_dsep_ptr;
+  std::vector<int64_t> dsep_poff, dsep_soff;
+  int64_t dsep_panel_total = 0, dsep_bits_total = 0;
+  std::vector<int32_t> seg_grp;               // group of each segment (its first column's group)
   int64_t crit_cols = 0;                      // sum over levels of the largest segment
   // solve: block levels of the back-substitution (blocks of a level are independent)
   std::vector<int32_t> blvl_ptr, blvl_blk;
