@@ -62,7 +62,13 @@ struct basker_ctx {
   DBuf<int64_t> dsep_poff, dsep_soff;
   DBuf<double> dpanel;
   DBuf<unsigned long long> dbits;
-  DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, blvl_blk, blvl_ctr;
+  DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, grpptr;
+  // solve tasks and ND group data of the solve
+  DBuf<int32_t> st_kind, st_id, st_need, sg_fd, sg_anc_ptr, sg_anc, sg_choff, s_rowpos, s_status;
+  DBuf<int64_t> sg_tbase;
+  DBuf<double> gbuf;
+  std::vector<int32_t> st_lvl_lds;   // LDS work doubles of every solve level
+  int32_t solve_lds_cap = 0;
   // numeric state
   DBuf<double> vals, Rx, OTx;
   DBuf<int32_t> pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
@@ -159,7 +165,6 @@ static basker_status upload_plan(basker_ctx* h) {
   }
   const int nb = (int)P.blkptr.size() - 1;
   const int nlev = (int)P.lvl_ptr.size() - 1;
-  const int nblev = (int)P.blvl_ptr.size() - 1;
   HIPCHK(h, h->Rp.upload(P.Rp, s));
   HIPCHK(h, h->Ri.upload(P.Ri, s));
   HIPCHK(h, h->Rmap.upload(P.Rmap, s));
@@ -200,8 +205,33 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->prow.upload(P.prow, s));
   HIPCHK(h, h->qcol.upload(P.qcol, s));
   HIPCHK(h, h->blkptr.upload(P.blkptr, s));
-  HIPCHK(h, h->blvl_blk.upload(P.blvl_blk, s));
-  HIPCHK(h, h->blvl_ctr.reserve(std::max(nblev, 1)));
+  HIPCHK(h, h->grpptr.upload(P.grpptr, s));
+  HIPCHK(h, h->st_kind.upload(P.st_kind, s));
+  HIPCHK(h, h->st_id.upload(P.st_id, s));
+  HIPCHK(h, h->st_need.upload(P.st_need, s));
+  HIPCHK(h, h->sg_fd.upload(P.sg_fd, s));
+  HIPCHK(h, h->sg_anc_ptr.upload(P.sg_anc_ptr, s));
+  HIPCHK(h, h->sg_anc.upload(P.sg_anc, s));
+  HIPCHK(h, h->sg_choff.upload(P.sg_choff, s));
+  HIPCHK(h, h->sg_tbase.upload(P.sg_tbase, s));
+  HIPCHK(h, h->s_rowpos.upload(P.s_rowpos, s));
+  HIPCHK(h, h->s_status.reserve(1));
+  {
+    // LDS per solve launch: the largest work area of the level that fits the device
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess)
+      lds_max = 65536;
+    lds_max = std::min(lds_max, 160 * 1024);
+    if (lds_max > 65536 && solve_lds_setup((size_t)lds_max) != hipSuccess) lds_max = 65536;
+    (void)hipGetLastError();
+    const size_t fixed = solve_lds_bytes(0);
+    h->solve_lds_cap = (int32_t)(((size_t)lds_max - fixed) / sizeof(double));
+    const int nsl = (int)P.st_lvl_ptr.size() - 1;
+    h->st_lvl_lds.assign(std::max(nsl, 0), 0);
+    for (int l = 0; l < nsl; l++)
+      for (int t = P.st_lvl_ptr[l]; t < P.st_lvl_ptr[l + 1]; t++)
+        if (P.st_need[t] <= h->solve_lds_cap) h->st_lvl_lds[l] = std::max(h->st_lvl_lds[l], P.st_need[t]);
+  }
   const int64_t nnzd = (int64_t)P.Ri.size();
   HIPCHK(h, h->vals.reserve(P.nnz));
   HIPCHK(h, h->Rx.reserve(nnzd));
@@ -279,7 +309,7 @@ static void fill_info_static(basker_ctx* h) {
   I.nd_blocks = P.n_nd_blocks;
   I.crit_cols = P.crit_cols;
   I.nlevels = (int32_t)P.lvl_ptr.size() - 1;
-  I.solve_levels = (int32_t)P.blvl_ptr.size() - 1;
+  I.solve_levels = (int32_t)P.st_lvl_ptr.size() - 1;
   I.fail_col = -1;
 }
 
@@ -544,38 +574,45 @@ extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, 
     dB = h->Bdev.p;
     ld = n;
   }
+  HIPCHK(h, h->gbuf.reserve(std::max<int64_t>(h->plan.s_gbuf_total * nrhs, 1)));
   SolveArgs a{};
   a.n = n;
   a.nrhs = nrhs;
   a.ldb = ld;
   a.blkptr = h->blkptr.p;
-  a.blvl_blk = h->blvl_blk.p;
-  a.lvl_ctr = h->blvl_ctr.p;
+  a.grpptr = h->grpptr.p;
+  a.st_kind = h->st_kind.p; a.st_id = h->st_id.p; a.st_need = h->st_need.p;
+  a.sg_fd = h->sg_fd.p; a.sg_anc_ptr = h->sg_anc_ptr.p; a.sg_anc = h->sg_anc.p;
+  a.sg_choff = h->sg_choff.p; a.sg_tbase = h->sg_tbase.p; a.rowpos = h->s_rowpos.p;
+  a.gbuf_total = h->plan.s_gbuf_total;
+  a.gbuf = h->gbuf.p;
   a.piv = h->piv.p;
   a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Li = h->Li.p; a.Lx = h->Lx.p;
   a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
   a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
   a.prow = h->prow.p; a.qcol = h->qcol.p;
   a.B = dB; a.W = h->W.p; a.Z = h->Z.p;
+  a.status = h->s_status.p;
   const Plan& P = h->plan;
-  const int nblev = (int)P.blvl_ptr.size() - 1;
-  HIPCHK(h, launch_fill_i32(h->blvl_ctr.p, 0, std::max(nblev, 1), s));
+  const int nsl = (int)P.st_lvl_ptr.size() - 1;
+  HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 1, s));
   HIPCHK(h, hipEventRecord(h->ev[2], s));
-  for (int l = 0; l < nblev; l++) {
-    a.level = l;
-    a.lvl_begin = P.blvl_ptr[l];
-    a.lvl_end = P.blvl_ptr[l + 1];
-    const int grid = std::min(a.lvl_end - a.lvl_begin, kNumCu * kWavesPerCu);
-    if (grid > 0) HIPCHK(h, launch_solve_level(a, grid, s));
+  for (int l = 0; l < nsl; l++) {
+    a.t_begin = P.st_lvl_ptr[l];
+    a.lds_doubles = h->st_lvl_lds[l];
+    HIPCHK(h, launch_solve_tasks(a, P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l], s));
   }
   HIPCHK(h, launch_solve_finish(a, s));
   HIPCHK(h, hipEventRecord(h->ev[3], s));
   if (!B_on_device)
     HIPCHK(h, hipMemcpy2DAsync(B, sizeof(double) * (size_t)ldb, h->Bdev.p, sizeof(double) * n, sizeof(double) * n,
                                nrhs, hipMemcpyDeviceToHost, s));
+  int32_t sst = 0;
+  HIPCHK(h, hipMemcpyAsync(&sst, h->s_status.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev[2], h->ev[3]) == hipSuccess) h->info.solve_kernel_ms = ms;
+  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve: factor entry outside its block or ND node rows");
   return BASKER_OK;
 }
 

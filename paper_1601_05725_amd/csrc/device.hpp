@@ -10,6 +10,9 @@
 #ifndef BASKER_SHARED
 #define BASKER_SHARED(type, name) __shared__ type name
 #endif
+#ifndef BASKER_DYN_SHARED
+#define BASKER_DYN_SHARED(type, name) extern __shared__ type name[]
+#endif
 
 namespace basker {
 
@@ -86,11 +89,22 @@ struct SolveArgs {
   int32_t nrhs;
   int32_t ldb;
   const int32_t* blkptr;
-  const int32_t* blvl_blk; // blocks of the launched level: blvl_blk[lvl_begin .. lvl_end)
-  int32_t lvl_begin;
-  int32_t lvl_end;
-  int32_t* lvl_ctr;        // one pop counter per level
-  int32_t level;
+  const int32_t* grpptr;
+  // tasks of the launched level: st_*[t_begin .. t_begin + grid)
+  const int32_t* st_kind;
+  const int32_t* st_id;
+  const int32_t* st_need;  // doubles of work storage; kept in LDS when <= lds_doubles
+  int32_t t_begin;
+  int32_t lds_doubles;
+  // ND groups: first descendant, ancestors (root first), ancestor-row offsets, areas
+  const int32_t* sg_fd;
+  const int32_t* sg_anc_ptr;
+  const int32_t* sg_anc;
+  const int32_t* sg_choff;
+  const int64_t* sg_tbase;
+  const int32_t* rowpos;
+  int64_t gbuf_total;      // doubles per right-hand side in gbuf
+  double* gbuf;            // [own rows | ancestor-row buffer] area of every ND group
   const int32_t* piv;
   const int32_t* Lbeg; const int32_t* Lcnt; const int32_t* Li; const double* Lx;
   const int32_t* Ubeg; const int32_t* Ucnt; const int32_t* Ui; const double* Ux;
@@ -102,6 +116,7 @@ struct SolveArgs {
   double* B;               // in/out, column-major (A numbering)
   double* W;               // n x nrhs scratch: residual in R-row numbering
   double* Z;               // n x nrhs scratch: solution in R-column numbering
+  int32_t* status;         // nonzero when an entry falls outside its task's rows
 };
 
 struct DenseSepArgs {
@@ -143,7 +158,9 @@ hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);
-hipError_t launch_solve_level(const SolveArgs& a, int grid, hipStream_t s);
+size_t solve_lds_bytes(int32_t work_doubles);
+hipError_t solve_lds_setup(size_t max_bytes);
+hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s);
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s);
 
 }  // namespace basker

@@ -836,6 +836,130 @@ void finish_schedule(Plan& P) {
 // Level lists of the factor segments (largest first inside a level) and of the
 // solve's block back-substitution: block b reads the solution of the later blocks its
 // off-diagonal entries touch, so level(b) = 1 + max level of those blocks.
+// Tasks of the block back-substitution.  R is block upper triangular, so block b can
+// start once every later block it couples to is solved.  A block without an ND tree
+// is one task (residual, L sweep, U sweep).  A block with an ND tree is split per
+// node: forward tasks from the leaves up (a node's L columns reach only its own rows
+// and its ancestors' rows; the latter go to a per-node buffer that the ancestors
+// add in a fixed order), then backward tasks from the root down (a node pulls the
+// products of its rows of the ancestors' U columns with the ancestors' solution).
+// A task's level is one more than the highest level of the tasks it waits for.
+void build_solve_tasks(Plan& P) {
+  const int n = P.n;
+  const int nb = (int)P.blkptr.size() - 1;
+  const int ng = (int)P.grpptr.size() - 1;
+  std::vector<int32_t> blk(n);
+  for (int b = 0; b < nb; b++)
+    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk[k] = b;
+  std::vector<int32_t> gfirst(nb + 1, 0);   // first group of every block
+  {
+    int g = 0;
+    for (int b = 0; b <= nb; b++) {
+      while (g < ng && P.grpptr[g] < (b < nb ? P.blkptr[b] : n)) g++;
+      gfirst[b] = g;
+    }
+  }
+  std::vector<char> is_nd(nb, 0);
+  if (!P.grp_parent.empty())
+    for (int b = 0; b < nb; b++)
+      for (int g = gfirst[b]; g < gfirst[b + 1]; g++)
+        if (P.grp_parent[g] >= 0) { is_nd[b] = 1; break; }
+  // group tree data: first descendant, ancestors (root first), ancestor row offsets
+  P.sg_fd.assign(ng, 0);
+  P.sg_choff.assign(ng, 0);
+  P.sg_tbase.assign(ng, 0);
+  P.sg_anc_ptr.assign(1, 0);
+  P.sg_anc.clear();
+  P.s_rowpos.assign(n, -1);
+  int64_t tb = 0;
+  for (int g = 0; g < ng; g++) P.sg_fd[g] = g;
+  for (int b = 0; b < nb; b++) {
+    for (int g = gfirst[b]; g < gfirst[b + 1]; g++) {
+      if (is_nd[b] && P.grp_parent[g] >= 0) {
+        const int p = P.grp_parent[g];
+        P.sg_fd[p] = std::min(P.sg_fd[p], P.sg_fd[g]);
+      }
+    }
+  }
+  for (int g = 0; g < ng; g++) {
+    std::vector<int32_t> chain;
+    int b = blk[P.grpptr[g]];
+    if (is_nd[b])
+      for (int a = P.grp_parent[g]; a >= 0; a = P.grp_parent[a]) chain.push_back(a);
+    int64_t off = 0;
+    for (int t = (int)chain.size() - 1; t >= 0; t--) {
+      P.sg_anc.push_back(chain[t]);
+      off += P.grpptr[chain[t] + 1] - P.grpptr[chain[t]];
+    }
+    P.sg_anc_ptr.push_back((int32_t)P.sg_anc.size());
+    P.sg_choff[g] = (int32_t)off;
+    if (is_nd[b]) {
+      P.sg_tbase[g] = tb;
+      tb += (P.grpptr[g + 1] - P.grpptr[g]) + off;
+      // a row's position in the ancestor-row buffer of any descendant of its group
+      for (int r = P.grpptr[g]; r < P.grpptr[g + 1]; r++) P.s_rowpos[r] = (int32_t)off + (r - P.grpptr[g]);
+    }
+  }
+  P.s_gbuf_total = tb;
+  // levels
+  std::vector<int32_t> base(nb, 0), done(nb, 0);
+  std::vector<int32_t> kind, id, lev;
+  std::vector<int32_t> fwd(ng, 0), bwd(ng, 0);
+  for (int c = nb - 1; c >= 0; c--) {
+    if (!is_nd[c]) {
+      kind.push_back(0); id.push_back(c); lev.push_back(base[c]);
+      done[c] = base[c];
+    } else {
+      int mx = base[c];
+      for (int g = gfirst[c]; g < gfirst[c + 1]; g++) fwd[g] = base[c];
+      for (int g = gfirst[c]; g < gfirst[c + 1]; g++) {   // postorder: children first
+        kind.push_back(1); id.push_back(g); lev.push_back(fwd[g]);
+        const int p = P.grp_parent[g];
+        if (p >= 0) fwd[p] = std::max(fwd[p], fwd[g] + 1);
+      }
+      for (int g = gfirst[c + 1] - 1; g >= gfirst[c]; g--) {  // parents first
+        const int p = P.grp_parent[g];
+        bwd[g] = (p >= 0 ? bwd[p] : fwd[g]) + 1;
+        kind.push_back(2); id.push_back(g); lev.push_back(bwd[g]);
+        mx = std::max(mx, bwd[g]);
+      }
+      done[c] = mx;
+    }
+    for (int k = P.blkptr[c]; k < P.blkptr[c + 1]; k++)
+      for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) {
+        const int b = blk[P.Oi[q]];
+        base[b] = std::max(base[b], done[c] + 1);
+      }
+  }
+  int nlev = 0;
+  for (int32_t l : lev) nlev = std::max(nlev, l + 1);
+  const int nt = (int)kind.size();
+  P.st_lvl_ptr.assign(nlev + 1, 0);
+  for (int t = 0; t < nt; t++) P.st_lvl_ptr[lev[t] + 1]++;
+  for (int l = 0; l < nlev; l++) P.st_lvl_ptr[l + 1] += P.st_lvl_ptr[l];
+  std::vector<int32_t> order(nt);
+  {
+    std::vector<int32_t> fp(P.st_lvl_ptr.begin(), P.st_lvl_ptr.end() - 1);
+    for (int t = 0; t < nt; t++) order[fp[lev[t]]++] = t;
+  }
+  auto tsize = [&](int t) {
+    return kind[t] == 0 ? P.blkptr[id[t] + 1] - P.blkptr[id[t]] : P.grpptr[id[t] + 1] - P.grpptr[id[t]];
+  };
+  for (int l = 0; l < nlev; l++)
+    std::stable_sort(order.begin() + P.st_lvl_ptr[l], order.begin() + P.st_lvl_ptr[l + 1],
+                     [&](int x, int y) { return tsize(x) > tsize(y); });
+  P.st_kind.resize(nt); P.st_id.resize(nt); P.st_need.resize(nt);
+  for (int q = 0; q < nt; q++) {
+    const int t = order[q];
+    P.st_kind[q] = kind[t];
+    P.st_id[q] = id[t];
+    const int m = tsize(t);
+    // doubles of work storage: block: residual/L part and U part; forward node: own
+    // rows and the ancestor-row buffer; backward node: own rows
+    P.st_need[q] = kind[t] == 0 ? 2 * m : kind[t] == 1 ? m + P.sg_choff[id[t]] : m;
+  }
+}
+
 void build_levels(Plan& P) {
   const int ns = (int)P.seg_c0.size();
   const int kDenseSepMin = 16;
@@ -933,34 +1057,7 @@ void build_levels(Plan& P) {
     }
     P.lvl_dsep_ptr.push_back((int32_t)P.dsep_seg.size());
   }
-  // solve levels over blocks (later blocks first)
-  const int nb = (int)P.blkptr.size() - 1;
-  std::vector<int32_t> blk(P.n);
-  for (int b = 0; b < nb; b++)
-    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk[k] = b;
-  std::vector<int32_t> lev(nb, 0);
-  int maxl = 0;
-  // entries of column k (block c) in rows of block b < c: b waits for c
-  // compute with the column-oriented off-diagonal part: for c from last to first, every
-  // row block b of column entries of c gets lev[b] >= lev[c] + 1
-  for (int c = nb - 1; c >= 0; c--) {
-    for (int k = P.blkptr[c]; k < P.blkptr[c + 1]; k++)
-      for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) {
-        int b = blk[P.Oi[q]];
-        if (lev[b] < lev[c] + 1) lev[b] = lev[c] + 1;
-      }
-    maxl = std::max(maxl, lev[c]);
-  }
-  P.blvl_ptr.assign(maxl + 2, 0);
-  for (int b = 0; b < nb; b++) P.blvl_ptr[lev[b] + 1]++;
-  for (int l = 0; l <= maxl; l++) P.blvl_ptr[l + 1] += P.blvl_ptr[l];
-  P.blvl_blk.assign(nb, 0);
-  std::vector<int32_t> fp(P.blvl_ptr.begin(), P.blvl_ptr.end() - 1);
-  for (int b = nb - 1; b >= 0; b--) P.blvl_blk[fp[lev[b]]++] = b;
-  for (int l = 0; l <= maxl; l++) {
-    auto bb = P.blvl_blk.begin() + P.blvl_ptr[l], ee = P.blvl_blk.begin() + P.blvl_ptr[l + 1];
-    std::stable_sort(bb, ee, [&](int x, int y) { return P.blkptr[x + 1] - P.blkptr[x] > P.blkptr[y + 1] - P.blkptr[y]; });
-  }
+  build_solve_tasks(P);
 }
 
 }  // namespace

@@ -66,8 +66,18 @@ struct Plan {
   int64_t dsep_panel_total = 0, dsep_bits_total = 0;
   std::vector<int32_t> seg_grp;               // group of each segment (its first column's group)
   int64_t crit_cols = 0;                      // sum over levels of the largest segment
-  // solve: block levels of the back-substitution (blocks of a level are independent)
-  std::vector<int32_t> blvl_ptr, blvl_blk;
+  // solve tasks in launch order: kind 0 = whole block (id = block), 1 = forward part of
+  // an ND node, 2 = backward part of an ND node (id = group); tasks of level l are
+  // [st_lvl_ptr[l], st_lvl_ptr[l+1]); st_need = doubles of work storage
+  std::vector<int32_t> st_kind, st_id, st_need, st_lvl_ptr;
+  // ND groups for the solve: first descendant group (postorder), ancestors root first
+  // (sg_anc[sg_anc_ptr[g] .. sg_anc_ptr[g+1])), total rows of the strict ancestors
+  // (sg_choff: also the offset of the group's rows in any descendant's buffer), and
+  // the offset of the group's [own rows | ancestor-row buffer] area (sg_tbase)
+  std::vector<int32_t> sg_fd, sg_anc_ptr, sg_anc, sg_choff;
+  std::vector<int64_t> sg_tbase;
+  std::vector<int32_t> s_rowpos;   // R row of an ND block -> sg_choff[its group] + offset in the group
+  int64_t s_gbuf_total = 0;
   int struct_rank = 0;
   double bottleneck = 0.0;
   int max_depth = 0;

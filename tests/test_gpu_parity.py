@@ -175,6 +175,13 @@ def test_nd_block(bk, orc):
     assert h.info()["nd_blocks"] >= 1
 
 
+def test_large_block_without_nd(bk, orc):
+    # one 11k-row block: its solve work vectors exceed LDS and live in global memory
+    a = synth.gen_mna(12000, seed=6)
+    h, order, ext = run_case(bk, orc, a, label="mna12k-no-nd", nd_min_block=10**9, nrhs=3)
+    assert np.diff(order.blkptr).max() > 10000
+
+
 def test_batched_btf_small(bk, orc):
     inp = synth.gen_batched_btf(nblocks=400, big=4000, seed=5)
     h, order, ext = run_case(bk, orc, inp.a, label="btf400", nd_min_block=2000, nd_leaves=4)
