@@ -12,6 +12,10 @@ a one-right-hand-side block back-substitution.  Workloads (see --workload):
   c0  one MNA circuit, n = 2,000
   c1  447 x 447 power-grid mesh with 2% long-range branches, ND with 16 leaves
   c3  MNA circuit n = 500,000; a step is a refactorization with new values + solve
+  c4  serving: a Poisson stream of factor / refactor / solve requests over many MNA
+      patterns (sizes log-uniform), served with concurrent slots against the plain
+      one-at-a-time path on the same arrival times (--rate, --requests, --patterns,
+      --nmax, --slots); prints requests/s and p50/p99 latency of both
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 """
@@ -83,6 +87,13 @@ def main():
     ap.add_argument("--workload", default=os.environ.get("BASKER_WORKLOAD", "c2"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=200.0, help="c4: arrivals per second")
+    ap.add_argument("--requests", type=int, default=2000, help="c4: requests in the stream")
+    ap.add_argument("--patterns", type=int, default=16, help="c4: distinct patterns")
+    ap.add_argument("--nmax", type=int, default=100000, help="c4: largest pattern order (smallest 1,000)")
+    ap.add_argument("--slots", type=int, default=8, help="c4: concurrent requests")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the factorization of one matrix is not split across GPUs "
@@ -95,7 +106,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes,
+                          "copies": 3}), flush=True)
+        return
     bk.load()
+    if args.workload == "c4":
+        return bench_serving(args)
 
     t = time.perf_counter()
     a, cfg, opts = make_workload(args.workload)
@@ -213,6 +237,121 @@ def main():
                                    reps, "refactor" if refactor else "factor", el)}
     h.free()
     print(json.dumps(out), flush=True)
+
+
+def serving_stream(args):
+    """Patterns (n log-uniform in [1000, nmax]) and a Poisson request stream: the first
+    request of a pattern is a factor, then 10% factor, 30% refactor (values scaled by
+    1 + 0.05 N(0,1)), 60% solve with 1..8 right-hand sides."""
+    import synth
+    from paper_1601_05725_amd import serve
+    rng = np.random.default_rng(160105725 + 4)
+    pats, state = [], {}
+    for i in range(args.patterns):
+        n = int(round(np.exp(rng.uniform(np.log(1000), np.log(args.nmax)))))
+        a = synth.gen_mna(n, seed=160105725 + 4 + 1000 * (i + 1))
+        key = "p%02d" % i
+        pats.append(serve.Pattern(key, a.n, a.colptr, a.rowind, a.values,
+                                  options=dict(nd_leaves=16) if a.n >= 10000 else {}))
+        state[key] = [a, a.values.copy(), False]
+    t = 0.0
+    reqs = []
+    for j in range(args.requests):
+        t += rng.exponential(1.0 / args.rate)
+        key = pats[int(rng.integers(len(pats)))].key
+        a, vals, touched = state[key]
+        u = rng.random()
+        if not touched or u < 0.1:
+            state[key][2] = True
+            reqs.append((t, serve.FACTOR, key, vals, None))
+        elif u < 0.4:
+            vals = vals * (1.0 + 0.05 * rng.standard_normal(vals.size))
+            state[key][1] = vals
+            reqs.append((t, serve.REFACTOR, key, vals, None))
+        else:
+            nrhs = int(rng.integers(1, 9))
+            reqs.append((t, serve.SOLVE, key, None, np.asfortranarray(rng.uniform(-1, 1, (a.n, nrhs)))))
+    return pats, reqs
+
+
+def bench_serving(args):
+    from paper_1601_05725_amd import serve
+    t = time.perf_counter()
+    pats, stream = serving_stream(args)
+    log("c4: %d patterns (n %d..%d), %d requests at %.0f/s generated in %.1fs" % (
+        len(pats), min(p.n for p in pats), max(p.n for p in pats), len(stream), args.rate, time.perf_counter() - t))
+
+    def requests():
+        return [serve.Request(kind, key, values=v, rhs=b) for (_, kind, key, v, b) in stream]
+
+    # symbolic analyses are resident before the stream starts (both paths)
+    srv = serve.Server(pats, slots=args.slots)
+    warm = [srv.submit(serve.Request(serve.FACTOR, p.key, values=p.values)) for p in pats]
+    for r in warm:
+        r.event.wait()
+    reqs = requests()
+    t0 = time.perf_counter()
+    for (ta, *_), r in zip(stream, reqs):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        r.arrival = t0 + ta
+        srv.submit(r)
+    for r in reqs:
+        r.event.wait()
+    served_wall = time.perf_counter() - t0
+    errors = sum(1 for r in reqs if r.error)
+    srv.close()
+
+    # plain path: one request at a time in arrival order on the same arrival times
+    handles = {}
+    base = requests()
+    for p in pats:
+        handles[p.key] = bk_handle(p)
+    t0 = time.perf_counter()
+    for (ta, *_), r in zip(stream, base):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        r.arrival = t0 + ta
+        h = handles[r.pattern]
+        r.start = time.perf_counter()
+        if r.kind == serve.FACTOR:
+            h.factor(r.values)
+        elif r.kind == serve.REFACTOR:
+            h.refactor(r.values)
+        else:
+            r.result = h.solve(r.rhs)
+        r.done = time.perf_counter()
+    plain_wall = time.perf_counter() - t0
+    for h in handles.values():
+        h.free()
+
+    def lat(rs):
+        x = np.array([r.latency for r in rs]) * 1e3
+        return float(np.percentile(x, 50)), float(np.percentile(x, 99))
+
+    p50, p99 = lat(reqs)
+    q50, q99 = lat(base)
+    nsolve = sum(1 for r in reqs if r.kind == serve.SOLVE)
+    out = {
+        "metric": "requests/s (served)", "value": len(reqs) / served_wall, "unit": "requests/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": len(pats), "ms_per_step": served_wall / len(reqs) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serving_%d_patterns_n1000_%d_rate%g" % (len(pats), args.nmax, args.rate),
+                   "requests": len(reqs), "slots": args.slots, "solves": nsolve},
+        "p50_ms": p50, "p99_ms": p99, "solves_per_s": nsolve / served_wall, "errors": errors,
+        "plain": {"value": len(base) / plain_wall, "p50_ms": q50, "p99_ms": q99, "solves_per_s": nsolve / plain_wall},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bk_handle(p):
+    import paper_1601_05725_amd as bk
+    from paper_1601_05725_amd import serve
+    h = bk.Handle.symbolic(serve._Csc(p), bk.default_options(**p.options))
+    h.factor(p.values)
+    return h
 
 
 if __name__ == "__main__":

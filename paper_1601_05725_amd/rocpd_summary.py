@@ -1,8 +1,22 @@
-"""Per-kernel duration summary (count, total, mean, min, max in microseconds) from a
-rocprofv3 --kernel-trace SQLite database (rocpd format)."""
+"""Profile summaries from rocprofv3 output.
+
+summarize(db): per-kernel duration summary (count, total, mean, min, max in
+microseconds) from a --kernel-trace SQLite database (rocpd format).
+
+pmc_passes(csv): per-dispatch counter values from a --pmc run written with -f csv
+(*_counter_collection.csv), cut into factorization passes (each pass starts at a
+factor_init_kernel dispatch); prints every kernel's value and the sum of the factor
+kernels of each complete pass.
+
+copy_counter(csv, name): the counter summed over the dispatches of the copy kernel of a
+calibration run.
+"""
+import csv
 import glob
 import sqlite3
 import sys
+
+FACTOR_KERNELS = ("factor_init_kernel", "factor_kernel", "sepdense_kernel")
 
 
 def summarize(path):
@@ -22,7 +36,51 @@ def summarize(path):
         print("%-60s %6d %12.1f %12.1f %12.1f %12.1f" % (name[:60], cnt, tot / 1e3, avg / 1e3, mn / 1e3, mx / 1e3))
 
 
+def _rows(path):
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            yield (int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]))
+
+
+def pmc_passes(path):
+    per = {}
+    for did, name, cname, val in _rows(path):
+        key = (did, name)
+        per[key] = per.get(key, 0.0) + val
+        counter = cname
+    disp = sorted(per.items())
+    passes, cur = [], None
+    for (did, name), val in disp:
+        if "factor_init_kernel" in name:
+            cur = []
+            passes.append(cur)
+        if cur is not None and any(k in name for k in FACTOR_KERNELS):
+            cur.append((did, name, val))
+    print("# %s  counter %s  (values as read, per dispatch)" % (path, counter))
+    for i, ps in enumerate(passes):
+        tot = sum(v for _, _, v in ps)
+        print("pass %d: %d dispatches, sum %.1f" % (i, len(ps), tot))
+        for did, name, val in ps:
+            print("   %8d %-60s %14.1f" % (did, name[:60], val))
+    return [sum(v for _, _, v in ps) for ps in passes]
+
+
+def copy_counter(path, name_part):
+    tot, n = 0.0, 0
+    for did, name, cname, val in _rows(path):
+        if name_part in name:
+            tot += val
+            n += 1
+    return tot, n
+
+
 if __name__ == "__main__":
+    if len(sys.argv) > 2 and sys.argv[1] == "--pmc":
+        pmc_passes(sys.argv[2])
+        sys.exit(0)
+    if len(sys.argv) > 3 and sys.argv[1] == "--copy":
+        print(copy_counter(sys.argv[2], sys.argv[3]))
+        sys.exit(0)
     for p in sys.argv[1:] or glob.glob("gpurun_out/**/*_results.db", recursive=True):
         print("#", p)
         summarize(p)
