@@ -58,6 +58,40 @@ def make_workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
+FACTOR_SOURCES = ("paper_1601_05725_amd/csrc/factor.hip", "paper_1601_05725_amd/csrc/sepdense.hip",
+                  "paper_1601_05725_amd/csrc/device.hpp")
+
+
+def factor_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in FACTOR_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(workload):
+    """HBM bytes per factorization measured by the FETCH_SIZE / WRITE_SIZE counter runs
+    summarised in profiles/, if they were taken on the current factor kernel sources
+    (else None: the kernels changed since)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha1") != factor_sources_sha1():
+        return None
+    try:
+        return float(vals["bytes_per_factorization"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(a, order, budget_s, refactor_piv=None):
     """The oracle (serial C, one core) on the same matrix and ordering: factor + solve
     repeated until about budget_s seconds are spent."""
@@ -222,7 +256,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": committed_traffic(args.workload),
             "algorithmic_bytes": bytes_factor,
         },
     }

@@ -63,7 +63,10 @@ typedef struct {
   double capacity_factor;  /* initial L/U pool = factor * nnz(diagonal blocks) (default 6; grows on overflow) */
   int32_t device;          /* HIP device ordinal (default 0); -1 = symbolic analysis only, no device work */
   void* stream;            /* hipStream_t to enqueue on; NULL = the handle's own stream */
-  int32_t reserved[8];
+  int32_t refactor_graph;  /* 1 (default): basker_refactor replays a HIP graph of its launches,
+                              captured on the first call and dropped by every full factorization;
+                              0: launch eagerly */
+  int32_t reserved[7];
 } basker_options;
 
 typedef struct {
@@ -91,7 +94,8 @@ typedef struct {
   int32_t nlevels;           /* factor level sets (ND tree height + 1, or 1 without ND) */
   int32_t solve_levels;      /* level sets of the block back-substitution */
   int64_t crit_cols;         /* columns on the factor's critical path: sum over levels of the largest segment */
-  int32_t reserved[11];
+  int64_t device_bytes;      /* device memory the handle holds now */
+  int32_t reserved[9];
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */

@@ -35,7 +35,8 @@ class basker_options(ctypes.Structure):
     _fields_ = [("pivot_tol", ctypes.c_double), ("diag_pref", ctypes.c_int32), ("matching", ctypes.c_int32),
                 ("btf", ctypes.c_int32), ("fill_order", ctypes.c_int32), ("nd_leaves", ctypes.c_int32),
                 ("nd_min_block", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 8)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("refactor_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class basker_info_t(ctypes.Structure):
@@ -48,7 +49,8 @@ class basker_info_t(ctypes.Structure):
                 ("factor_calls", ctypes.c_int32), ("refactor_calls", ctypes.c_int32),
                 ("refactor_fallbacks", ctypes.c_int32), ("pool_regrows", ctypes.c_int32),
                 ("nd_blocks", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("solve_levels", ctypes.c_int32),
-                ("crit_cols", ctypes.c_int64), ("reserved", ctypes.c_int32 * 11)]
+                ("crit_cols", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 9)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

@@ -17,13 +17,23 @@ using namespace basker;
 
 namespace {
 
+// device bytes are charged to the handle whose call is running on this thread
+thread_local int64_t* t_acct = nullptr;
+struct AcctScope {
+  int64_t* prev;
+  explicit AcctScope(int64_t* a) : prev(t_acct) { t_acct = a; }
+  ~AcctScope() { t_acct = prev; }
+};
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
   int64_t cap = 0;
+  int64_t* acct = nullptr;   // device-byte counter of the owning handle
   ~DBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
+    if (p && acct) *acct -= (int64_t)sizeof(T) * cap;
     p = nullptr;
     cap = 0;
   }
@@ -34,6 +44,8 @@ struct DBuf {
     hipError_t e = hipMalloc((void**)&p, sizeof(T) * (size_t)m);
     if (e != hipSuccess) { p = nullptr; return e; }
     cap = m;
+    acct = t_acct;
+    if (acct) *acct += (int64_t)sizeof(T) * cap;
     return hipSuccess;
   }
   hipError_t upload(const std::vector<T>& v, hipStream_t s) {
@@ -46,7 +58,11 @@ struct DBuf {
 }  // namespace
 
 struct basker_ctx {
+  int64_t dev_bytes = 0;     // declared first: buffers release into it when destroyed
   int device = 0;
+  // refactorization graph: scatter + init + level launches, reading h->vals
+  hipGraph_t rgraph = nullptr;
+  hipGraphExec_t rgexec = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   basker_options opt{};
@@ -120,6 +136,7 @@ extern "C" basker_status basker_default_options(basker_options* o) {
   o->capacity_factor = 6.0;
   o->device = 0;
   o->stream = nullptr;
+  o->refactor_graph = 1;
   return BASKER_OK;
 }
 
@@ -143,6 +160,7 @@ extern "C" const char* basker_last_error(basker_handle h) { return h ? h->err.c_
 // Everything the device needs from the plan, plus the solve's row-wise coupling and
 // block dependency lists.
 static basker_status upload_plan(basker_ctx* h) {
+  AcctScope acct(&h->dev_bytes);
   Plan& P = h->plan;
   const int n = P.n;
   hipStream_t s = h->stream;
@@ -409,15 +427,14 @@ static basker_status stage_values(basker_ctx* h, const double* values, int32_t o
   return BASKER_OK;
 }
 
-// one device pass; fills st[ST_WORDS], the pool extents and the stored nnz counts
-static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st, unsigned long long* poolc,
-                                       unsigned long long* nnzc) {
+// the launches of one device pass (init, then every level); returns the first error
+static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
   hipStream_t s = h->stream;
   FactorArgs a = factor_args(h, refactor);
   const Plan& P = h->plan;
   const int nlev = (int)P.lvl_ptr.size() - 1;
-  HIPCHK(h, launch_factor_init(a, nlev, s));
-  HIPCHK(h, hipEventRecord(h->ev[0], s));
+  hipError_t e = launch_factor_init(a, nlev, s);
+  if (e != hipSuccess) return e;
   DenseSepArgs dA{};
   dA.dsep_seg = h->dsep_seg.p; dA.seg_c0 = h->seg_c0.p; dA.seg_c1 = h->seg_c1.p; dA.dsep_H = h->dsep_H.p;
   dA.rng_ptr = h->dsep_rng_ptr.p; dA.rng_g0 = h->dsep_rng_g0.p; dA.rng_len = h->dsep_rng_len.p;
@@ -436,7 +453,7 @@ static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st,
       a.mode = 0;
       a.level = l;
       const int grid = std::min(a.item_end - a.item_begin, h->grid);
-      if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
+      if (grid > 0 && (e = launch_factor_level(a, grid, s)) != hipSuccess) return e;
       continue;
     }
     // separator level (Alg. 4): the descendant part of every separator column in
@@ -447,33 +464,86 @@ static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st,
     a.col_begin = P.lvl_col_ptr[l];
     a.col_end = refactor ? P.lvl_col_ptr[l] + P.lvl_dcol_cnt[l] : P.lvl_col_ptr[l + 1];
     int grid = std::min(a.col_end - a.col_begin, h->grid);
-    if (grid > 0) HIPCHK(h, launch_factor_level(a, grid, s));
+    if (grid > 0 && (e = launch_factor_level(a, grid, s)) != hipSuccess) return e;
     a.level = l;
     grid = std::min(a.item_end - a.item_begin, kNumCu * 3);
     if (grid > 0) {
       if (refactor) {
         a.mode = 0;
-        HIPCHK(h, launch_factor_level(a, std::min(grid, h->grid), s));
+        if ((e = launch_factor_level(a, std::min(grid, h->grid), s)) != hipSuccess) return e;
       } else {
         a.mode = 2;
-        HIPCHK(h, launch_factor_sep_step2(a, grid, s));
+        if ((e = launch_factor_sep_step2(a, grid, s)) != hipSuccess) return e;
       }
     }
     dA.d_begin = P.lvl_dsep_ptr[l];
-    HIPCHK(h, launch_sepdense(dA, P.lvl_dsep_ptr[l + 1] - P.lvl_dsep_ptr[l], s));
+    if ((e = launch_sepdense(dA, P.lvl_dsep_ptr[l + 1] - P.lvl_dsep_ptr[l], s)) != hipSuccess) return e;
   }
-  HIPCHK(h, hipEventRecord(h->ev[1], s));
+  return hipSuccess;
+}
+
+// status words, pool extents and stored nnz counts of the pass just enqueued
+static basker_status read_factor_status(basker_ctx* h, int32_t* st, unsigned long long* poolc,
+                                        unsigned long long* nnzc) {
+  hipStream_t s = h->stream;
   HIPCHK(h, hipMemcpyAsync(st, h->status.p, sizeof(int32_t) * ST_WORDS, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(poolc, h->pool.p, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(nnzc, h->nnz_ctr.p, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  return BASKER_OK;
+}
+
+// one device pass; fills st[ST_WORDS], the pool extents and the stored nnz counts
+static basker_status run_factor_kernel(basker_ctx* h, int refactor, int32_t* st, unsigned long long* poolc,
+                                       unsigned long long* nnzc) {
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipEventRecord(h->ev[0], s));
+  HIPCHK(h, enqueue_factor(h, refactor));
+  HIPCHK(h, hipEventRecord(h->ev[1], s));
+  basker_status r = read_factor_status(h, st, poolc, nnzc);
+  if (r != BASKER_OK) return r;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->info.factor_kernel_ms = ms;
   if (hipEventElapsedTime(&ms, h->ev[4], h->ev[5]) == hipSuccess) h->info.scatter_kernel_ms = ms;
   return BASKER_OK;
 }
 
+static void drop_refactor_graph(basker_ctx* h) {
+  if (h->rgexec) (void)hipGraphExecDestroy(h->rgexec);
+  if (h->rgraph) (void)hipGraphDestroy(h->rgraph);
+  h->rgexec = nullptr;
+  h->rgraph = nullptr;
+}
+
+// capture the refactorization launches (value scatter from h->vals, init, levels)
+static bool capture_refactor_graph(basker_ctx* h) {
+  hipStream_t s = h->stream;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  hipError_t e = launch_scatter(h->vals.p, h->Rmap.p, h->Rx.p, (int64_t)h->plan.Ri.size(), s);
+  if (e == hipSuccess) e = launch_scatter(h->vals.p, h->OTmap.p, h->OTx.p, (int64_t)h->plan.Oi.size(), s);
+  if (e == hipSuccess) e = enqueue_factor(h, 1);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x) {
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  h->rgraph = g;
+  h->rgexec = x;
+  return true;
+}
 static basker_status do_factor(basker_ctx* h) {
+  drop_refactor_graph(h);   // pools may move
   for (int attempt = 0; attempt < 8; attempt++) {
     int32_t st[ST_WORDS];
     unsigned long long poolc[3], nnzc[2];
@@ -525,6 +595,7 @@ static basker_status do_factor(basker_ctx* h) {
 
 extern "C" basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device) {
   if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
+  AcctScope acct(&h->dev_bytes);
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   HIPCHK(h, hipSetDevice(h->device));
   basker_status r = stage_values(h, values, values_on_device);
@@ -534,15 +605,38 @@ extern "C" basker_status basker_factor(basker_handle h, const double* values, in
 
 extern "C" basker_status basker_refactor(basker_handle h, const double* values, int32_t values_on_device) {
   if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
+  AcctScope acct(&h->dev_bytes);
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "refactor before a successful factor");
   HIPCHK(h, hipSetDevice(h->device));
-  basker_status r = stage_values(h, values, values_on_device);
-  if (r != BASKER_OK) return r;
   int32_t st[ST_WORDS];
   unsigned long long poolc[3], nnzc[2];
-  r = run_factor_kernel(h, 1, st, poolc, nnzc);
-  if (r != BASKER_OK) return r;
+  basker_status r = BASKER_OK;
+  bool graphed = false;
+  if (h->opt.refactor_graph) {
+    // the graph reads the values from the handle's buffer
+    hipStream_t s = h->stream;
+    if (h->plan.nnz > 0 && values != h->vals.p)
+      HIPCHK(h, hipMemcpyAsync(h->vals.p, values, sizeof(double) * (size_t)h->plan.nnz,
+                               values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (h->rgexec || capture_refactor_graph(h)) {
+      HIPCHK(h, hipEventRecord(h->ev[0], s));
+      HIPCHK(h, hipGraphLaunch(h->rgexec, s));
+      HIPCHK(h, hipEventRecord(h->ev[1], s));
+      r = read_factor_status(h, st, poolc, nnzc);
+      if (r != BASKER_OK) return r;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->info.factor_kernel_ms = ms;
+      h->info.scatter_kernel_ms = 0.0;   // inside the graph, counted in factor_kernel_ms
+      graphed = true;
+    }
+  }
+  if (!graphed) {
+    r = stage_values(h, values, values_on_device);
+    if (r != BASKER_OK) return r;
+    r = run_factor_kernel(h, 1, st, poolc, nnzc);
+    if (r != BASKER_OK) return r;
+  }
   h->info.refactor_calls++;
   if (st[ST_CODE] == DEV_OK) return BASKER_OK;
   h->info.fail_col = st[ST_FAILCOL] == 0x7fffffff ? -1 : st[ST_FAILCOL];
@@ -557,6 +651,7 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
 
 extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb, int32_t B_on_device) {
   if (!h || nrhs < 0 || (nrhs > 0 && !B) || ldb < h->plan.n) return BASKER_ERR_INVALID;
+  AcctScope acct(&h->dev_bytes);
   if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "solve before a successful factor");
   if (nrhs == 0 || h->plan.n == 0) return BASKER_OK;
   HIPCHK(h, hipSetDevice(h->device));
@@ -619,6 +714,7 @@ extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, 
 extern "C" basker_status basker_info(basker_handle h, basker_info_t* info) {
   if (!h || !info) return BASKER_ERR_INVALID;
   *info = h->info;
+  info->device_bytes = h->dev_bytes;
   return BASKER_OK;
 }
 
@@ -694,6 +790,7 @@ extern "C" void basker_free(basker_handle h) {
   if (h->device < 0) { delete h; return; }
   (void)hipSetDevice(h->device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  drop_refactor_graph(h);
   for (auto& ev : h->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

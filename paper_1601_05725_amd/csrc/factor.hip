@@ -33,25 +33,46 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
-// One workgroup is one wavefront, so no hardware barrier is needed between lanes;
-// what is needed is that every LDS and global access issued before this point has
-// completed before any lane continues (lanes exchange data through LDS and, across
-// columns, through the global arrays).  The fence keeps the compiler from moving
-// memory operations across; the wait drains all outstanding memory counters.
+// One workgroup is one wavefront.  Lanes exchange data through LDS and, across
+// columns, through global memory; the lanes of one wavefront need no cache action to
+// see each other's writes (one vector L1 per CU, memory instructions of a wavefront
+// performed in order), so a wavefront-scope fence, which only keeps the compiler
+// from moving memory operations across it, is all the ordering required.
 __device__ __forceinline__ void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v) {
+__device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ double rl_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// exclusive prefix sum of v over lanes [0, nb) (nb uniform, <= 64; v = 0 on lanes
+// >= nb): scalar reads of the few lanes when nb is small, a shuffle scan otherwise
+__device__ __forceinline__ int excl_scan(int v, int nb) {
   const int lane = lane_id();
+  if (nb <= 16) {
+    int acc = 0;
+    for (int u = 0; u < nb; u++) {
+      const int x = rl(v, u);
+      if (u < lane) acc += x;
+    }
+    return acc;
+  }
+  int x = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    int t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
+    const int t = __shfl_up(x, d, 64);
+    if (lane >= d) x += t;
   }
-  return v;
+  return x - v;
 }
 
 __device__ __forceinline__ int ld_relaxed(int32_t* p) {
@@ -71,6 +92,12 @@ struct Ws {
   int32_t* pc;    //    L(:,j) length
   unsigned long long* sk;  // H: sorted (j << 32 | list index)
   int32_t* cnt;   // [0] inserted, [1] pivotal, [2] overflow
+  // staging of the update's L entries (always in LDS): workspace slot and value,
+  // offsets and global starts of the staged columns
+  int32_t* st_slot;
+  double* st_val;
+  int32_t* st_pre;
+  int32_t* st_beg;
   int H;
   int shift;      // 32 - log2(H)
 };
@@ -84,6 +111,8 @@ struct Alloc {
   int offdiag;
 };
 
+constexpr int kStage = 512;   // staged L entries per pass of the update
+
 template <int H>
 struct LdsWs {
   int32_t key[H];
@@ -95,6 +124,10 @@ struct LdsWs {
   int32_t pb[H];
   int32_t pc[H];
   unsigned long long sk[H];
+  double st_val[kStage];
+  int32_t st_slot[kStage];
+  int32_t st_pre[72];
+  int32_t st_beg[64];
   int32_t cnt[4];
 };
 
@@ -160,21 +193,13 @@ __device__ __forceinline__ void plist_push(const Ws& w, int32_t j, int slot) {
 // ascending.  Keys are distinct.  Bitonic network in registers (np <= 64) or LDS.
 __device__ void plist_sort(const Ws& w, int np) {
   const int lane = lane_id();
+  np = uniform(np);
   if (np <= 64) {
-    unsigned long long v = ~0ull;
-    if (lane < np) v = ((unsigned long long)(unsigned)w.pj[lane] << 32) | (unsigned)lane;
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        unsigned long long o = __shfl_xor(v, j, 64);
-        bool up = ((lane & k) == 0);
-        bool lower = ((lane & j) == 0);
-        unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
-        v = (lower == up) ? mn : mx;
-      }
-    }
-    if (lane < np) w.sk[lane] = v;
+    // rank of every key among the np distinct keys, read lane by lane
+    const unsigned key = lane < np ? (unsigned)w.pj[lane] : 0xffffffffu;
+    int rank = 0;
+    for (int u = 0; u < np; u++) rank += ((unsigned)rl((int)key, u) < key) ? 1 : 0;
+    if (lane < np) w.sk[rank] = ((unsigned long long)key << 32) | (unsigned)lane;
     wsync();
     return;
   }
@@ -200,40 +225,56 @@ __device__ void plist_sort(const Ws& w, int np) {
 
 // Expand the frontier entries [f0, f1) of the pivotal list: record each entry's
 // L column and insert its rows.  New pivotal rows join the list (next frontier).
-__device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1) {
+// plim: rows whose pivot column is >= plim count as not pivotal (see factor_column)
+__device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1, int plim) {
   const int lane = lane_id();
   for (int c0 = f0; c0 < f1; c0 += 64) {
+    const int nb = uniform(f1 - c0 < 64 ? f1 - c0 : 64);
     const int e = c0 + lane;
     int beg = 0, cnt = 0;
-    if (e < f1) {
+    if (lane < nb) {
       const int j = w.pj[e];
       beg = a.Lbeg[j];
       cnt = a.Lcnt[j];
       w.pb[e] = beg;
       w.pc[e] = cnt;
     }
-    const int incl = wave_incl_scan(cnt);
-    const int excl = incl - cnt;
-    const int total = __shfl(incl, 63, 64);
+    const int excl = excl_scan(cnt, nb);
+    const int total = rl(excl, nb - 1) + rl(cnt, nb - 1);
+    if (nb > 8) {
+      if (lane < nb) {
+        w.st_pre[lane] = excl;
+        w.st_beg[lane] = beg;
+      }
+      wsync();
+    }
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
-      // owner lane: largest o with excl_o <= t
-      int o = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        int cand = o + step;
-        int ex = __shfl(excl, cand & 63, 64);
-        if (cand < 64 && ex <= t) o = cand;
+      // owner: the last list entry whose first position is <= t
+      int ob = 0, oe = 0;
+      if (nb <= 8) {
+        for (int u = 0; u < nb; u++) {
+          const int ex = rl(excl, u);
+          const int bu = rl(beg, u);
+          if (ex <= t) { ob = bu; oe = ex; }
+        }
+      } else {
+        int lo = 0, hi = nb;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (w.st_pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        ob = w.st_beg[lo];
+        oe = w.st_pre[lo];
       }
-      const int ob = __shfl(beg, o, 64);
-      const int oe = __shfl(excl, o, 64);
       if (t < total) {
         const int32_t r = a.Li[ob + (t - oe)];
         bool isnew;
         int slot = ws_insert(w, r, &isnew);
         if (slot >= 0 && isnew) {
           w.val[slot] = 0.0;
-          const int32_t pvr = a.pinv[r];
+          int32_t pvr = a.pinv[r];
+          if (pvr >= plim) pvr = -1;
           w.pv[slot] = pvr;
           if (pvr >= 0) plist_push(w, pvr, slot);
         }
@@ -263,14 +304,56 @@ __device__ __forceinline__ long long pool_take(long long* cur, long long* end, l
   return off;
 }
 
-__device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al) {
+// The next column's entries of R, loaded while the current column runs (a column of a
+// segment in mode 0): offsets at the start, rows and values after the reach, and the
+// rows' pivot columns after the update.  Between that last load and the next column only
+// the current column's own pivot row changes its pivot column (no other wavefront
+// pivots rows of this segment), so that one row is patched on use.
+struct Pre {
+  int k;        // column the data belongs to, -1 for none
+  int b, e;     // R(:,k) = entries [b, e), at most 64
+  int32_t r;    // the lane's row
+  double x;     // the lane's value
+  int32_t pv;   // pivot column of the lane's row when loaded
+  int pp, pk;   // pivot row and index of the column during which pv was loaded
+};
+
+__device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al, Pre& pre, int knext) {
   const int lane = lane_id();
   ws_reset(w);
   const int g0 = a.grp_lo[k], g1 = a.grp_hi[k];
+  // The first step of a separator level (mode 1) applies only the pivots of the
+  // separator's descendants, whose columns precede the separator's first column g0.  In
+  // a factorization no other row is pivotal yet; a refactorization keeps the previous
+  // pivots of every row, so later pivots (the separator's own and its ancestors') must
+  // be read as not pivotal here.
+  const int plim = a.mode == 1 ? g0 : 0x7fffffff;
+  const bool use_pre = a.mode == 0 && !a.refactor && pre.k == k;
+  const Pre cur = pre;
+  const bool do_pre = a.mode == 0 && !a.refactor && knext >= 0;
+  pre.k = -1;
+  if (do_pre) {
+    pre.b = a.Rp[knext];
+    pre.e = a.Rp[knext + 1];
+    if (pre.e - pre.b <= 64) pre.k = knext;
+  }
 
   int ub = 0, uc = 0, lb = 0, lc = 0, p = -1;
   if (!a.refactor || a.mode == 1) {
-    if (a.mode != 2) {
+    if (use_pre) {
+      // struct(R(:,k)) with values, loaded during the previous column
+      if (lane < cur.e - cur.b) {
+        const int32_t r = cur.r;
+        bool isnew;
+        int slot = ws_insert(w, r, &isnew);
+        if (slot >= 0) {
+          w.val[slot] = cur.x;
+          const int32_t pvr = (r == cur.pp) ? cur.pk : cur.pv;
+          w.pv[slot] = pvr;
+          if (pvr >= 0) plist_push(w, pvr, slot);
+        }
+      }
+    } else if (a.mode != 2) {
       // struct(R(:,k)) with values
       for (int q = a.Rp[k] + lane; q < a.Rp[k + 1]; q += 64) {
         const int32_t r = a.Ri[q];
@@ -278,7 +361,8 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
         int slot = ws_insert(w, r, &isnew);
         if (slot >= 0) {
           w.val[slot] = a.Rx[q];
-          const int32_t pvr = a.pinv[r];
+          int32_t pvr = a.pinv[r];
+          if (pvr >= plim) pvr = -1;
           w.pv[slot] = pvr;
           if (pvr >= 0) plist_push(w, pvr, slot);
         }
@@ -304,7 +388,7 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
     int f1 = w.cnt[1];
     while (f0 < f1) {
       if (w.cnt[2]) break;
-      expand_frontier(a, w, f0, f1);
+      expand_frontier(a, w, f0, f1, plim);
       f0 = f1;
       f1 = w.cnt[1];
     }
@@ -352,6 +436,10 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
     wsync();
   }
 
+  if (pre.k >= 0 && lane < pre.e - pre.b) {
+    pre.r = a.Ri[pre.b + lane];
+    pre.x = a.Rx[pre.b + lane];
+  }
   // topological order: ascending pivot column
   const int np = w.cnt[1];
   if (!a.refactor || a.mode == 1) {
@@ -361,22 +449,92 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
     wsync();
   }
 
-  // sparse triangular update
-  for (int e = 0; e < np; e++) {
-    const int src = (int)(w.sk[e] & 0xffffffffu);
-    const int s = w.ps[src];
-    const int beg = w.pb[src];
-    const int c = w.pc[src];
-    const double xj = w.val[s];
-    for (int t = lane; t < c; t += 64) {
-      const int32_t r = a.Li[beg + t];
-      const double l = a.Lx[beg + t];
-      const int slot = ws_lookup(w, r);
-      const double prod = l * xj;
-      if (slot >= 0) w.val[slot] = w.val[slot] - prod;
-      else w.cnt[3] = 1;
+  // sparse triangular update, ascending pivot order.  The L(:,j) entries of up to 64
+  // list entries at a time are gathered into LDS in one wave-wide pass, their rows
+  // resolved to workspace slots on the way, then applied column by column from LDS.
+  for (int e0 = 0; e0 < np; e0 += 64) {
+    const int nb = uniform(np - e0 < 64 ? np - e0 : 64);
+    int c = 0, beg = 0, sl = 0;
+    if (lane < nb) {
+      const int src = (int)(w.sk[e0 + lane] & 0xffffffffu);
+      sl = w.ps[src];
+      beg = w.pb[src];
+      c = w.pc[src];
     }
-    wsync();
+    const int off = excl_scan(c, nb);
+    int j0 = 0;
+    while (j0 < nb) {
+      const int off0 = rl(off, j0);
+      const bool fit = lane >= j0 && lane < nb && off + c - off0 <= kStage;
+      const int nfit = __popcll(__ballot(fit));
+      if (nfit == 0) {
+        // a column longer than the stage: straight from global memory
+        const int cj = rl(c, j0), bj = rl(beg, j0);
+        const double xj = w.val[rl(sl, j0)];
+        for (int t = lane; t < cj; t += 64) {
+          const int slot = ws_lookup(w, a.Li[bj + t]);
+          const double prod = a.Lx[bj + t] * xj;
+          if (slot >= 0) w.val[slot] = w.val[slot] - prod;
+          else w.cnt[3] = 1;
+        }
+        wsync();
+        j0++;
+        continue;
+      }
+      const int j1 = j0 + nfit;
+      if (lane >= j0 && lane < j1) {
+        w.st_pre[lane - j0] = off - off0;
+        w.st_beg[lane - j0] = beg;
+      }
+      if (lane == j1 - 1) w.st_pre[j1 - j0] = off + c - off0;
+      wsync();
+      const int total = rl(off, j1 - 1) + rl(c, j1 - 1) - off0;
+      const int nc = j1 - j0;
+      for (int base = 0; base < total; base += 64 * 8) {
+        int gi[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int q = base + u * 64 + lane;
+          gi[u] = -1;
+          if (q < total) {
+            int lo = 0, hi = nc;
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (w.st_pre[mid] <= q) lo = mid; else hi = mid;
+            }
+            gi[u] = w.st_beg[lo] + (q - w.st_pre[lo]);
+          }
+        }
+        int32_t rr[8];
+        double xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          rr[u] = 0;
+          xx[u] = 0.0;
+          if (gi[u] >= 0) { rr[u] = a.Li[gi[u]]; xx[u] = a.Lx[gi[u]]; }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int q = base + u * 64 + lane;
+          if (gi[u] >= 0) { w.st_slot[q] = ws_lookup(w, rr[u]); w.st_val[q] = xx[u]; }
+        }
+      }
+      wsync();
+      for (int j = j0; j < j1; j++) {
+        const int cj = rl(c, j);
+        if (cj == 0) continue;
+        const int o = rl(off, j) - off0;
+        const double xj = w.val[rl(sl, j)];
+        for (int t = lane; t < cj; t += 64) {
+          const int slot = w.st_slot[o + t];
+          const double prod = w.st_val[o + t] * xj;
+          if (slot >= 0) w.val[slot] = w.val[slot] - prod;
+          else w.cnt[3] = 1;
+        }
+        wsync();
+      }
+      j0 = j1;
+    }
   }
   if (w.cnt[3]) {
     if (lane == 0) {
@@ -427,6 +585,7 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
     }
     return 0;
   }
+  if (pre.k >= 0 && lane < pre.e - pre.b) pre.pv = a.pinv[pre.r];
   // pivot search over the candidates of the column's group
   double best = -1.0;
   int bidx = 0x7fffffff;
@@ -441,14 +600,30 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
       if (r == k) { has_diag = 1; xd = w.val[s]; }
     }
   }
+  {
+    // combine the lanes' partial results (only lanes below nins hold candidates)
+    const int nl = uniform(nins < 64 ? nins : 64);
+    if (nl <= 16) {
+      double gb = -1.0;
+      int gi = 0x7fffffff;
+      for (int u = 0; u < nl; u++) {
+        const double ob = rl_d(best, u);
+        const int oi = rl(bidx, u);
+        if (ob > gb || (ob == gb && oi < gi)) { gb = ob; gi = oi; }
+      }
+      best = gb;
+      bidx = gi;
+    } else {
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) {
-    const double ob = __shfl_xor(best, d, 64);
-    const int oi = __shfl_xor(bidx, d, 64);
-    if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      for (int d = 32; d > 0; d >>= 1) {
+        const double ob = __shfl_xor(best, d, 64);
+        const int oi = __shfl_xor(bidx, d, 64);
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      }
+    }
   }
   const unsigned long long dmask = __ballot(has_diag);
-  if (dmask) xd = __shfl(xd, __ffsll((long long)dmask) - 1, 64);
+  if (dmask) xd = rl_d(xd, __ffsll((long long)dmask) - 1);
   const double m = best;   // -1 when there is no candidate
 
   if (!a.refactor) {
@@ -543,6 +718,8 @@ __device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al)
     }
   }
   if (lane == 0) a.pinv[p] = k;
+  pre.pp = p;
+  pre.pk = k;
   return 0;
 }
 
@@ -555,6 +732,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   Ws wl;
   wl.key = lds.key; wl.val = lds.val; wl.pv = lds.pv; wl.ins = lds.ins; wl.pj = lds.pj;
   wl.ps = lds.ps; wl.pb = lds.pb; wl.pc = lds.pc; wl.sk = lds.sk; wl.cnt = lds.cnt;
+  wl.st_slot = lds.st_slot; wl.st_val = lds.st_val; wl.st_pre = lds.st_pre; wl.st_beg = lds.st_beg;
   wl.H = HS;
   wl.shift = 32 - __builtin_ctz(HS);
   Ws wg;
@@ -571,11 +749,16 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.pc = (int32_t*)(base + 32ll * H);
     wg.sk = (unsigned long long*)(base + 40ll * H);
     wg.cnt = (int32_t*)(base + 48ll * H);
+    wg.st_slot = lds.st_slot; wg.st_val = lds.st_val; wg.st_pre = lds.st_pre; wg.st_beg = lds.st_beg;
     wg.H = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
   }
   wsync();
   Alloc al = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  Pre pre;
+  pre.k = -1;
+  pre.pp = -1;
+  pre.pk = -1;
   if (a.mode == 1) {
     // one column at a time: every column of the level's separators is independent here
     const int ncols = a.col_end - a.col_begin;
@@ -586,9 +769,9 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
       if (idx >= ncols) break;
       if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
       const int k = a.col_list[a.col_begin + idx];
-      int rc = factor_column(a, wl, k, al);
+      int rc = factor_column(a, wl, k, al, pre, -1);
       if (rc == 1) {
-        rc = factor_column(a, wg, k, al);
+        rc = factor_column(a, wg, k, al, pre, -1);
         if (rc == 1 && lane == 0) {
           atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
           atomicMin(&a.status[ST_FAILCOL], k);
@@ -609,10 +792,12 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
       for (int q = a.item_lo[it]; q < a.item_hi[it]; q++) {
         const int sg = a.lvl_seg[q];
         const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];
+        pre.k = -1;
         for (int k = c0; k < c1; k++) {
-          int rc = factor_column(a, wl, k, al);
+          const int knext = k + 1 < c1 ? k + 1 : -1;
+          int rc = factor_column(a, wl, k, al, pre, knext);
           if (rc == 1) {
-            rc = factor_column(a, wg, k, al);
+            rc = factor_column(a, wg, k, al, pre, knext);
             if (rc == 1 && lane == 0) {
               atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
               atomicMin(&a.status[ST_FAILCOL], k);
@@ -637,11 +822,17 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
 
 __global__ void factor_init_kernel(FactorArgs a, int32_t nlevels) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n && !a.refactor) a.pinv[i] = -1;
+  if (i < a.n && !a.refactor) {
+    a.pinv[i] = -1;
+    a.Lbeg[i] = 0; a.Lcnt[i] = 0; a.Ubeg[i] = 0; a.Ucnt[i] = 0;
+  }
   if (i < ST_WORDS) a.status[i] = (i == ST_FAILCOL) ? 0x7fffffff : 0;
   if (i < 2 * nlevels) a.lvl_ctr[i] = 0;
+  // the separator partial-column buffer is refilled on every pass; the L/U pools keep
+  // their columns in a refactorization
+  if (i == 0) a.pool_next[2] = 0;
   if (i == 0 && !a.refactor) {
-    a.pool_next[0] = 0; a.pool_next[1] = 0; a.pool_next[2] = 0; a.nnz_ctr[0] = 0; a.nnz_ctr[1] = 0;
+    a.pool_next[0] = 0; a.pool_next[1] = 0; a.nnz_ctr[0] = 0; a.nnz_ctr[1] = 0;
   }
 }
 

@@ -215,6 +215,49 @@ def test_refactor_bitwise_and_sequence(bk, orc):
         assert orc.residual(at, h.solve(b), b) <= RES_TOL
 
 
+def test_refactor_graph_replays_match_eager(bk, orc):
+    """Refactorizations replayed from the captured HIP graph against eager launches on a
+    second handle: every replay bitwise equal, with eager work and host synchronisation
+    between replays, device- and host-resident values, and a forced fallback (which
+    drops the graph) in the middle of the sequence."""
+    import torch
+    a = synth.gen_mna(12000, seed=6)
+    og = bk.default_options(nd_min_block=3000, nd_leaves=8)
+    oe = bk.default_options(nd_min_block=3000, nd_leaves=8)
+    oe.refactor_graph = 0
+    hg = bk.Handle.symbolic(a, og)
+    he = bk.Handle.symbolic(a, oe)
+    hg.factor(a.values)
+    he.factor(a.values)
+    seq = list(synth.value_sequence(a, 6))
+    replays = 0
+    for t, vals in enumerate(seq):
+        if t == 3:
+            # a tiny pivot in the first column of the ND block forces the threshold
+            # check to fail on both handles
+            vals = vals.copy()
+            prow, qcol, bp, gp = hg.ordering()
+            k = int(bp[np.argmax(np.diff(bp))])
+            acol, arow = int(qcol[k]), int(prow[hg.extract().piv[k]])
+            q = a.colptr[acol] + int(np.nonzero(a.rowind[a.colptr[acol]:a.colptr[acol + 1]] == arow)[0][0])
+            vals[q] *= 1e-14
+        say("graph/eager refactor step %d" % t)
+        v = torch.from_numpy(vals).cuda() if t % 2 == 0 else vals
+        sg = hg.refactor(v)
+        se = he.refactor(vals)
+        assert sg == se
+        if t == 3:
+            assert sg == bk.REFACTOR_FELL_BACK
+        else:
+            replays += int(sg == bk.OK)
+        compare_exact(hg.extract(), he.extract())
+        b = synth.rhs(a.n, 1, ident=100 + t)
+        np.testing.assert_array_equal(hg.solve(b), he.solve(b))
+        torch.cuda.synchronize()
+    assert hg.info()["refactor_calls"] == he.info()["refactor_calls"] == 6
+    assert replays >= 3
+
+
 def test_refactor_fallback_forced(bk, orc):
     a = synth.gen_mna(400, seed=10)
     order = orc.Ordering.natural(a.n)
