@@ -318,7 +318,8 @@ struct Pre {
   int pp, pk;   // pivot row and index of the column during which pv was loaded
 };
 
-__device__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al, Pre& pre, int knext) {
+__device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al, Pre& pre,
+                                             int knext) {
   const int lane = lane_id();
   ws_reset(w);
   const int g0 = a.grp_lo[k], g1 = a.grp_hi[k];
