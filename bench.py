@@ -75,7 +75,10 @@ def committed_traffic(workload):
     """HBM bytes per factorization measured by the FETCH_SIZE / WRITE_SIZE counter runs
     summarised in profiles/, if they were taken on the current factor kernel sources
     (else None: the kernels changed since)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_%s.txt" % workload)
+    names = {"c2": "factor_traffic_batched_btf_c2.txt"}
+    if workload not in names:
+        return None
+    path = os.path.join(ROOT, "profiles", names[workload])
     if not os.path.exists(path):
         return None
     vals = {}
