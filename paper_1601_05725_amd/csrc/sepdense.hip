@@ -281,20 +281,39 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
     if (tid == 0) piv_bits[p >> 6] |= 1ull << (p & 63);
     __syncthreads();
     // ---- rank-1 update of every later column whose pivot-row entry is structural
+    // (columns k and cc are distinct, so their panel columns do not overlap: the loads of
+    // four words are issued together before the stores)
+    const double* __restrict__ Lk = P + (int64_t)k * H;
     for (int cc = k + 1 + wv; cc < m; cc += nw) {
-      unsigned long long* Sc = S + (int64_t)cc * W;
+      unsigned long long* __restrict__ Sc = S + (int64_t)cc * W;
       if (!((Sc[p >> 6] >> (p & 63)) & 1ull)) continue;
-      double* Pc = P + (int64_t)cc * H;
+      double* __restrict__ Pc = P + (int64_t)cc * H;
       const double u = Pc[p];
-      for (int w = 0; w < W; w++) {
+      for (int w = lane; w < W; w += 64) {
         const unsigned long long b = lbits[w];
-        if (!b) continue;
-        const int r = (w << 6) + lane;
-        if ((b >> lane) & 1ull) {
-          const double prod = P[r + (int64_t)k * H] * u;
-          Pc[r] = Pc[r] - prod;
+        if (b) Sc[w] |= b;
+      }
+      for (int w0 = 0; w0 < W; w0 += 4) {
+        double lv[4], cv[4];
+        bool on[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int w = w0 + t;
+          on[t] = w < W && ((lbits[w] >> lane) & 1ull);
+          lv[t] = 0.0;
+          cv[t] = 0.0;
+          if (on[t]) {
+            lv[t] = Lk[(w << 6) + lane];
+            cv[t] = Pc[(w << 6) + lane];
+          }
         }
-        if (lane == 0) Sc[w] |= b;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          if (on[t]) {
+            const double prod = lv[t] * u;
+            Pc[((w0 + t) << 6) + lane] = cv[t] - prod;
+          }
+        }
       }
     }
     __syncthreads();
