@@ -463,8 +463,8 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     a.level = nlev + l;
     a.col_begin = P.lvl_col_ptr[l];
     a.col_end = refactor ? P.lvl_col_ptr[l] + P.lvl_dcol_cnt[l] : P.lvl_col_ptr[l + 1];
-    int grid = std::min(a.col_end - a.col_begin, h->grid);
-    if (grid > 0 && (e = launch_factor_level(a, grid, s)) != hipSuccess) return e;
+    int grid = std::min(std::min(a.col_end - a.col_begin, h->grid), kNumCu);
+    if (grid > 0 && (e = launch_factor_sep_step1(a, grid, s)) != hipSuccess) return e;
     a.level = l;
     grid = std::min(a.item_end - a.item_begin, kNumCu * 3);
     if (grid > 0) {

@@ -19,6 +19,8 @@ namespace basker {
 constexpr int kWave = 64;
 constexpr int kLdsSlots = 512;        // per-wave LDS hash slots (power of two)
 constexpr int kLdsSlotsSep = 1024;    // larger table for separator columns (mode 2)
+constexpr int kLdsSlotsStep1 = 4096;  // the column-parallel first step of separator levels
+                                      // (one workgroup per CU: ~135 KB of LDS)
 constexpr int kWavesPerCu = 6;        // persistent-grid occupancy target
 constexpr int kNumCu = 256;
 
@@ -155,6 +157,7 @@ struct DenseSepArgs {
 hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s);
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
+hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);

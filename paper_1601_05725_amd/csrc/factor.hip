@@ -27,6 +27,8 @@
 // ascending pivot order.
 #include "device.hpp"
 
+#define COMMA ,
+
 namespace basker {
 
 namespace {
@@ -99,6 +101,7 @@ struct Ws {
   int32_t* st_pre;
   int32_t* st_beg;
   int H;
+  int NP;         // capacity of the pivotal list
   int shift;      // 32 - log2(H)
 };
 
@@ -113,17 +116,19 @@ struct Alloc {
 
 constexpr int kStage = 512;   // staged L entries per pass of the update
 
-template <int H>
+// H hash slots; the pivotal list holds NP entries (a column overflows to the global
+// workspace once more than H/2 rows are inserted, so NP = H/2 is always enough)
+template <int H, int NP>
 struct LdsWs {
   int32_t key[H];
   double val[H];
   int32_t pv[H];
   int32_t ins[H];
-  int32_t pj[H];
-  int32_t ps[H];
-  int32_t pb[H];
-  int32_t pc[H];
-  unsigned long long sk[H];
+  int32_t pj[NP];
+  int32_t ps[NP];
+  int32_t pb[NP];
+  int32_t pc[NP];
+  unsigned long long sk[NP];
   double st_val[kStage];
   int32_t st_slot[kStage];
   int32_t st_pre[72];
@@ -183,6 +188,10 @@ __device__ __forceinline__ void ws_reset(const Ws& w) {
 
 __device__ __forceinline__ void plist_push(const Ws& w, int32_t j, int slot) {
   int e = atomicAdd(&w.cnt[1], 1);
+  if (e >= w.NP) {   // only past the overflow point; the column moves to the global workspace
+    w.cnt[2] = 1;
+    return;
+  }
   w.pj[e] = j;
   w.ps[e] = slot;
   w.pb[e] = 0;
@@ -724,9 +733,9 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
   return 0;
 }
 
-template <int HS>
+template <int HS, int NPS>
 __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
-  BASKER_SHARED(LdsWs<HS>, lds);
+  BASKER_SHARED(LdsWs<HS COMMA NPS>, lds);
   const int lane = lane_id();
   for (int t = lane; t < HS; t += 64) lds.key[t] = -1;
   if (lane == 0) { lds.cnt[0] = 0; lds.cnt[1] = 0; lds.cnt[2] = 0; lds.cnt[3] = 0; }
@@ -735,6 +744,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   wl.ps = lds.ps; wl.pb = lds.pb; wl.pc = lds.pc; wl.sk = lds.sk; wl.cnt = lds.cnt;
   wl.st_slot = lds.st_slot; wl.st_val = lds.st_val; wl.st_pre = lds.st_pre; wl.st_beg = lds.st_beg;
   wl.H = HS;
+  wl.NP = NPS;
   wl.shift = 32 - __builtin_ctz(HS);
   Ws wg;
   {
@@ -752,6 +762,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.cnt = (int32_t*)(base + 48ll * H);
     wg.st_slot = lds.st_slot; wg.st_val = lds.st_val; wg.st_pre = lds.st_pre; wg.st_beg = lds.st_beg;
     wg.H = H;
+    wg.NP = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
   }
   wsync();
@@ -860,12 +871,17 @@ hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t 
 }
 
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(factor_kernel<kLdsSlots>, dim3(grid), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((factor_kernel<kLdsSlots, kLdsSlots>), dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((factor_kernel<kLdsSlotsStep1, kLdsSlotsStep1 / 2>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(factor_kernel<kLdsSlotsSep>, dim3(grid), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((factor_kernel<kLdsSlotsSep, kLdsSlotsSep>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
