@@ -24,6 +24,16 @@ namespace {
 
 constexpr int kDT = 1024;          // threads per workgroup
 constexpr int kMaxRowWords = 256;  // panel rows up to 16,384
+constexpr int kMaxPivl = 4096;     // local pivots kept in LDS for separators up to this size
+
+__device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ double rl_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 __device__ __forceinline__ int local_row(const DenseSepArgs& a, int d, int32_t r) {
   for (int t = a.rng_ptr[d]; t < a.rng_ptr[d + 1]; t++) {
@@ -44,6 +54,8 @@ __device__ __forceinline__ int32_t global_row(const DenseSepArgs& a, int d, int 
 __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
   __shared__ unsigned long long piv_bits[kMaxRowWords];   // rows already pivotal
   __shared__ unsigned long long lbits[kMaxRowWords];      // rows of L(:,k)
+  __shared__ unsigned long long sk_s[kMaxRowWords];       // structure of column k
+  __shared__ int pivl_s[kMaxPivl];                        // local pivot rows (m <= kMaxPivl)
   __shared__ double red_v[kDT / 64];
   __shared__ int red_i[kDT / 64];
   __shared__ int sh_p, sh_fail, sh_hasdiag;
@@ -134,6 +146,7 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
         sh_p = p;
         sh_xp = Pk[p];
         pivl[k] = p;
+        if (m <= kMaxPivl) pivl_s[k] = p;
       }
     }
     __syncthreads();
@@ -142,6 +155,7 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
     const double xp = sh_xp;
     // ---- rows of L(:,k): structural, not pivotal, not the pivot
     for (int w = tid; w < W; w += kDT) {
+      sk_s[w] = Sk[w];
       unsigned long long b = Sk[w] & ~piv_bits[w];
       if ((p >> 6) == w) b &= ~(1ull << (p & 63));
       lbits[w] = b;
@@ -156,8 +170,8 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
         const int j = j0 + lane;
         bool in = false;
         if (j < k) {
-          const int pr = pivl[j];
-          in = (Sk[pr >> 6] >> (pr & 63)) & 1ull;
+          const int pr = m <= kMaxPivl ? pivl_s[j] : pivl[j];
+          in = (sk_s[pr >> 6] >> (pr & 63)) & 1ull;
         }
         nu += __popcll(__ballot(in));
       }
@@ -200,8 +214,8 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
           bool in = false;
           int pr = 0;
           if (j < k) {
-            pr = pivl[j];
-            in = (Sk[pr >> 6] >> (pr & 63)) & 1ull;
+            pr = m <= kMaxPivl ? pivl_s[j] : pivl[j];
+            in = (sk_s[pr >> 6] >> (pr & 63)) & 1ull;
           }
           const unsigned long long bm = __ballot(in);
           if (in) {
@@ -284,34 +298,49 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
     // (columns k and cc are distinct, so their panel columns do not overlap: the loads of
     // four words are issued together before the stores)
     const double* __restrict__ Lk = P + (int64_t)k * H;
-    for (int cc = k + 1 + wv; cc < m; cc += nw) {
-      unsigned long long* __restrict__ Sc = S + (int64_t)cc * W;
-      if (!((Sc[p >> 6] >> (p & 63)) & 1ull)) continue;
-      double* __restrict__ Pc = P + (int64_t)cc * H;
-      const double u = Pc[p];
-      for (int w = lane; w < W; w += 64) {
-        const unsigned long long b = lbits[w];
-        if (b) Sc[w] |= b;
+    // this wave's later columns cc = k + 1 + wv + nw * t, 64 at a time: one lane per
+    // column tests the pivot row's structure bit and loads the multiplier, then the
+    // columns with the bit set are updated one after another by the whole wave
+    for (int t0 = 0; k + 1 + wv + nw * t0 < m; t0 += 64) {
+      const int ccl = k + 1 + wv + nw * (t0 + lane);
+      bool on = false;
+      double ul = 0.0;
+      if (ccl < m) {
+        on = (S[(int64_t)ccl * W + (p >> 6)] >> (p & 63)) & 1ull;
+        if (on) ul = P[(int64_t)ccl * H + p];
       }
-      for (int w0 = 0; w0 < W; w0 += 4) {
-        double lv[4], cv[4];
-        bool on[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-          const int w = w0 + t;
-          on[t] = w < W && ((lbits[w] >> lane) & 1ull);
-          lv[t] = 0.0;
-          cv[t] = 0.0;
-          if (on[t]) {
-            lv[t] = Lk[(w << 6) + lane];
-            cv[t] = Pc[(w << 6) + lane];
-          }
+      unsigned long long act = __ballot(on);
+      while (act) {
+        const int j = __ffsll((long long)act) - 1;
+        act &= act - 1;
+        const int cc = rl(ccl, j);
+        const double u = rl_d(ul, j);
+        unsigned long long* __restrict__ Sc = S + (int64_t)cc * W;
+        double* __restrict__ Pc = P + (int64_t)cc * H;
+        for (int w = lane; w < W; w += 64) {
+          const unsigned long long b = lbits[w];
+          if (b) Sc[w] |= b;
         }
+        for (int w0 = 0; w0 < W; w0 += 4) {
+          double lv[4], cv[4];
+          bool onw[4];
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-          if (on[t]) {
-            const double prod = lv[t] * u;
-            Pc[((w0 + t) << 6) + lane] = cv[t] - prod;
+          for (int t = 0; t < 4; t++) {
+            const int w = w0 + t;
+            onw[t] = w < W && ((lbits[w] >> lane) & 1ull);
+            lv[t] = 0.0;
+            cv[t] = 0.0;
+            if (onw[t]) {
+              lv[t] = Lk[(w << 6) + lane];
+              cv[t] = Pc[(w << 6) + lane];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            if (onw[t]) {
+              const double prod = lv[t] * u;
+              Pc[((w0 + t) << 6) + lane] = cv[t] - prod;
+            }
           }
         }
       }
