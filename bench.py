@@ -141,7 +141,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the factorization of one matrix is not split across GPUs "
-              "in this build (multi-GPU sharding is a design note); use --gpus 1", file=sys.stderr)
+              "by this library (multi-GPU sharding is a design note); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

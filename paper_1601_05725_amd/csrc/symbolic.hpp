@@ -2,7 +2,7 @@
 //
 // Builds R = A(prow, qcol) in block upper triangular form (Sec. III-A: a bottleneck
 // matching puts large entries on the diagonal, then strongly connected components
-// give the diagonal blocks), orders every small block for fill (Alg. 2, line 2) and
+// give the diagonal blocks), orders every small block for fill (Alg. 2) and
 // the large blocks by nested dissection with a fill order inside every node
 // (Sec. III-C), and derives the candidate groups (pivots stay inside a BTF block or
 // an ND node) and the column dependency forest the numeric kernels schedule on.

@@ -81,6 +81,6 @@ if __name__ == "__main__":
     if len(sys.argv) > 3 and sys.argv[1] == "--copy":
         print(copy_counter(sys.argv[2], sys.argv[3]))
         sys.exit(0)
-    for p in sys.argv[1:] or glob.glob("gpurun_out/**/*_results.db", recursive=True):
+    for p in sys.argv[1:] or glob.glob("**/*_results.db", recursive=True):
         print("#", p)
         summarize(p)
