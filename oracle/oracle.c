@@ -268,11 +268,24 @@ or_result *or_factor(int n, const int32_t *Ap, const int32_t *Ai, const double *
             if (diag_pref && diag_cand && fabs(x[k]) >= tau * m) p = k;
             else p = argmax;
         }
-        /* decision margin (relative to m) of the choice just made */
+        /* decision margin (relative to m) of the choice just made.  For tau <= 1 the
+         * diagonal test |x_k| >= tau * m passes exactly when |x_k| >= tau * m_o, with
+         * m_o the largest candidate magnitude other than row k (row k itself can never
+         * fail against its own magnitude), so its margin is measured against m_o; a
+         * diagonal that is the only candidate is decided outright.  The argmax choice,
+         * when it matters, is measured by the gap to the runner-up. */
         {
             double mu = INFINITY;
             if (m > 0.0) {
-                if (diag_pref && diag_cand) mu = fabs(fabs(x[k]) - tau * m) / m;
+                if (diag_pref && diag_cand) {
+                    double mo = -1.0;
+                    for (int t = top; t < n; t++) {
+                        int i = pattern[t];
+                        if (pinv[i] >= 0 || i < g0 || i >= g1 || i == k) continue;
+                        if (fabs(x[i]) > mo) mo = fabs(x[i]);
+                    }
+                    if (mo >= 0.0) mu = fabs(fabs(x[k]) - tau * mo) / m;
+                }
                 if (!(diag_pref && diag_cand && fabs(x[k]) >= tau * m)) {
                     double m2 = 0.0; int any2 = 0;
                     for (int t = top; t < n; t++) {

@@ -31,40 +31,77 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # independent dense reference (right-looking elimination, original row space)
 # ---------------------------------------------------------------------------
 
-def dense_threshold_lu(R, blkptr, grpptr, tau, diag_pref):
+def dense_threshold_lu(R, blkptr, grpptr, tau, diag_pref, stats=None):
     """Dense right-looking LU of the block-diagonal part of R with the pivot rule of
-    the sparse path.  Returns (status, fail_col, piv, L, U) with L, U in pivot order."""
+    the sparse path.  Returns (status, fail_col, piv, L, U) with L, U in pivot order.
+
+    With a dict ``stats`` it also records, by their definitions and from this
+    elimination alone:
+      * ``margin[k]``: the decision margin of column k's pivot choice, clipped at 1.
+        With C the non-pivotal rows of k's group and m = max |x_C|: if the diagonal
+        test applies (diag_pref, k in C) it passes iff |x_k| >= tau * m_o, m_o the
+        largest magnitude over C minus row k, so its margin is | |x_k| - tau m_o | / m;
+        when the pivot is not the preferred diagonal, the argmax also matters, with
+        margin (m - m2) / m, m2 the runner-up.  No competitor gives margin 1.
+      * ``flops``: multiply-subtract pairs (2 flops each) applied to structurally
+        nonzero entries plus one division per entry of L, counted as the
+        right-looking elimination performs them.
+    Structure is tracked symbolically (an entry is structural if it is in the input
+    or receives an update), so an entry whose value cancels to zero stays in L or U,
+    as the sparse factorization keeps it.
+    """
     n = R.shape[0]
     A = np.zeros_like(R)
     for b in range(len(blkptr) - 1):
         s, e = blkptr[b], blkptr[b + 1]
         A[s:e, s:e] = R[s:e, s:e]
+    S = A != 0.0
     grp = np.repeat(np.arange(len(grpptr) - 1), np.diff(grpptr))
     blk = np.repeat(np.arange(len(blkptr) - 1), np.diff(blkptr))
     pivoted = np.zeros(n, bool)
     piv = np.zeros(n, np.int64)
     Lrow = np.zeros((n, n))
     Urows = np.zeros((n, n))
+    margin = np.ones(n)
+    flops = 0
     for k in range(n):
         cand = np.nonzero((~pivoted) & (grp == grp[k]))[0]
         x = A[:, k]
         m = np.abs(x[cand]).max() if cand.size else 0.0
         if not m > 0:
             return -3, k, None, None, None
-        if diag_pref and (not pivoted[k]) and grp[k] == grp[k] and abs(x[k]) >= tau * m:
+        dtest = diag_pref and not pivoted[k]
+        amax = int(cand[np.nonzero(np.abs(x[cand]) == m)[0][0]])
+        if dtest and abs(x[k]) >= tau * m:
             p = k
         else:
-            p = int(cand[np.nonzero(np.abs(x[cand]) == m)[0][0]])
+            p = amax
+        mu = 1.0
+        if dtest:
+            others = cand[cand != k]
+            if others.size:
+                mu = min(mu, abs(abs(x[k]) - tau * np.abs(x[others]).max()) / m)
+        if p != k or not dtest:
+            others = cand[cand != amax]
+            if others.size:
+                mu = min(mu, (m - np.abs(x[others]).max()) / m)
+        margin[k] = mu
         piv[k] = p
         pivoted[p] = True
         Urows[k, k:] = A[p, k:]
         rows = np.nonzero((~pivoted) & (blk == blk[k]))[0]
+        ucnt = int(np.count_nonzero(S[p, k + 1:] & (blk[k + 1:] == blk[k])))
         for i in rows:
-            if A[i, k] != 0.0:
+            if S[i, k]:
                 l = A[i, k] / A[p, k]
                 Lrow[i, k] = l
+                flops += 1 + 2 * ucnt
                 A[i, k + 1:] = A[i, k + 1:] - l * A[p, k + 1:]
+                S[i, k + 1:] |= S[p, k + 1:]
                 A[i, k] = 0.0
+    if stats is not None:
+        stats["margin"] = margin
+        stats["flops"] = flops
     pos = np.empty(n, np.int64)
     pos[piv] = np.arange(n)
     L = np.eye(n)
@@ -430,14 +467,99 @@ def test_p8_solve_block_triangular(oracle_lib):
 # update order: DFS reverse postorder vs ascending pivot index
 # ---------------------------------------------------------------------------
 
-def test_update_orders_agree(oracle_lib):
+@pytest.mark.parametrize("tau", [1.0, 0.1, 0.001])
+def test_update_orders_agree(oracle_lib, tau):
+    """Two topological update orders of the same elimination: no column of these MNA
+    cases has an ambiguous decision, so pivots and patterns agree exactly and values
+    to rounding."""
     a = synth.gen_mna(800, seed=12)
-    f0 = oracle_lib.factor(a, update_order=0)
-    f1 = oracle_lib.factor(a, update_order=1)
-    amb = f0.margin < 1e-10
-    assert np.array_equal(f0.piv[~amb], f1.piv[~amb]) or amb.any()
-    if np.array_equal(f0.piv, f1.piv):
-        for x, y in ((f0.Lp, f1.Lp), (f0.Li, f1.Li), (f0.Up, f1.Up), (f0.Ui, f1.Ui)):
-            np.testing.assert_array_equal(x, y)
-        assert np.abs(f0.Lx - f1.Lx).max() <= 1e-12 * max(1, np.abs(f0.Lx).max())
-        assert np.abs(f0.Ux - f1.Ux).max() <= 1e-12 * max(1, np.abs(f0.Ux).max())
+    f0 = oracle_lib.factor(a, tau=tau, update_order=0)
+    f1 = oracle_lib.factor(a, tau=tau, update_order=1)
+    assert not np.any(f0.margin < 1e-10) and not np.any(f1.margin < 1e-10)
+    np.testing.assert_array_equal(f0.piv, f1.piv)
+    for x, y in ((f0.Lp, f1.Lp), (f0.Li, f1.Li), (f0.Up, f1.Up), (f0.Ui, f1.Ui)):
+        np.testing.assert_array_equal(x, y)
+    assert np.abs(f0.Lx - f1.Lx).max() <= 1e-12 * max(1, np.abs(f0.Lx).max())
+    assert np.abs(f0.Ux - f1.Ux).max() <= 1e-12 * max(1, np.abs(f0.Ux).max())
+
+
+# ---------------------------------------------------------------------------
+# decision margins and the flop count, against the dense elimination
+# ---------------------------------------------------------------------------
+
+def test_margin_golden(oracle_lib):
+    """Hand-derived margins (tests/golden/margins.txt) on tiny integer matrices with
+    exact ties, an exact threshold equality and clear decisions."""
+    for line in open(os.path.join(GOLDEN, "margins.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        head, mat, want = line.split("|")
+        name, n, tau, dp = head.split()
+        n = int(n)
+        A = np.array([float(v) for v in mat.split()]).reshape(n, n)
+        f = oracle_lib.factor(synth.csc_from_dense(A), tau=float(tau), diag_pref=bool(int(dp)))
+        assert f.status == 0, name
+        np.testing.assert_allclose(f.margin, [float(v) for v in want.split()], rtol=1e-15, atol=0, err_msg=name)
+
+
+def _margin_case(oracle_lib, D, blkptr, grpptr, tau, dp):
+    n = D.shape[0]
+    a = synth.csc_from_dense(D)
+    order = oracle_lib.Ordering(np.arange(n), np.arange(n), blkptr, grpptr)
+    st = {}
+    ds, _, dpiv, _, _ = dense_threshold_lu(D, blkptr, grpptr, tau, dp, stats=st)
+    f = oracle_lib.factor(a, order, tau=tau, diag_pref=dp)
+    assert f.status == ds == 0
+    np.testing.assert_array_equal(f.piv, dpiv)
+    return f, st
+
+
+@pytest.mark.parametrize("seed", list(range(20, 28)))
+@pytest.mark.parametrize("diag_pref,tau", [(False, 1.0), (True, 1.0), (True, 0.5), (True, 0.1)])
+def test_margin_vs_dense_integer(oracle_lib, seed, diag_pref, tau):
+    """{-1, 0, 1} matrices with a nonzero diagonal (so a non-pivotal diagonal row is
+    always structurally present): exact ties and threshold equalities occur, and
+    every margin equals the one the dense elimination derives by definition."""
+    n = 12
+    s = synth.Stream(synth.substream_key(seed, 5))
+    D = s.integers(-1, 2, n * n).astype(float).reshape(n, n)
+    D[np.arange(n), np.arange(n)] = np.where(s.uniform(n) < 0.5, 1.0, -1.0)
+    f, st = _margin_case(oracle_lib, D, np.array([0, n]), np.array([0, n]), tau, diag_pref)
+    np.testing.assert_allclose(np.minimum(f.margin, 1.0), st["margin"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+@pytest.mark.parametrize("tau", [1.0, 0.1])
+def test_margin_and_flops_vs_dense_groups(oracle_lib, seed, tau):
+    """Random sparse matrices (continuous values, no exact cancellation) with blocks and
+    candidate groups: margins agree with the dense definition to rounding, and the flop
+    count F equals the dense elimination's count of structural multiply-subtracts and
+    divisions exactly."""
+    n = 48
+    a0 = synth.random_sparse(n, 0.12, seed)
+    blkptr, grpptr = _groups_case(n, seed)
+    D = _block_upper(a0.to_dense(), blkptr)
+    f, st = _margin_case(oracle_lib, D, blkptr, grpptr, tau, True)
+    np.testing.assert_allclose(np.minimum(f.margin, 1.0), st["margin"], rtol=0, atol=1e-12)
+    assert f.flops == st["flops"]
+    f0 = oracle_lib.factor(synth.csc_from_dense(D), oracle_lib.Ordering(np.arange(n), np.arange(n), blkptr, grpptr),
+                           tau=tau, update_order=oracle_lib.ORDER_DFS)
+    assert f0.flops == st["flops"]
+
+
+def test_flops_closed_form_dense(oracle_lib):
+    """Fully dense n x n with partial pivoting: sum_k (n-k-1) (1 + 2 (n-k-1)) flops."""
+    n = 20
+    A = synth.random_dense(n, 3)
+    f = oracle_lib.factor(synth.csc_from_dense(A), tau=1.0, diag_pref=False)
+    want = sum((n - k - 1) * (1 + 2 * (n - k - 1)) for k in range(n))
+    assert f.flops == want
+
+
+def test_margin_rarely_ambiguous_on_mna(oracle_lib):
+    """Continuous circuit values: ambiguous decisions (margin < 1e-10) are absent."""
+    for n, seed in ((300, 21), (2000, 160105725)):
+        a = synth.gen_mna(n, seed=seed)
+        for tau in (1.0, 0.1, 0.001):
+            f = oracle_lib.factor(a, tau=tau)
+            assert np.count_nonzero(f.margin < 1e-10) == 0, (n, tau)
