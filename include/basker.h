@@ -66,7 +66,13 @@ typedef struct {
   int32_t refactor_graph;  /* 1 (default): basker_refactor replays a HIP graph of its launches,
                               captured on the first call and dropped by every full factorization;
                               0: launch eagerly */
-  int32_t reserved[7];
+  int32_t max_grid;        /* cap on the workgroups of the factor launches (0 = the device's
+                              occupancy target); results do not depend on it */
+  int64_t hbm_budget;      /* bytes of device memory the handle may hold (0 = unlimited): an
+                              allocation beyond it fails the call with BASKER_ERR_OOM */
+  int32_t sched_flags;     /* bit 0: hand out the work items of every level in reverse order;
+                              results do not depend on it (a check of determinism) */
+  int32_t reserved[3];
 } basker_options;
 
 typedef struct {
@@ -95,11 +101,20 @@ typedef struct {
   int32_t solve_levels;      /* level sets of the block back-substitution */
   int64_t crit_cols;         /* columns on the factor's critical path: sum over levels of the largest segment */
   int64_t device_bytes;      /* device memory the handle holds now */
-  int32_t reserved[9];
+  int32_t dense_seps;        /* ND separators the last factorization ran on the dense kernel */
+  int32_t sparse_seps;       /* ND separators of the plan factored column by column */
+  int64_t device_bytes_plan; /* device memory the handle is expected to hold after its first
+                                factorization and a solve with 8 right-hand sides (set by the
+                                symbolic analysis, also for device = -1; pool growth on an
+                                underestimated fill adds to it) */
+  int32_t reserved[8];
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */
 basker_status basker_default_options(basker_options* o);
+
+/* Every call that takes options rejects pivot_tol outside (0, 1], nd_leaves < 1 or
+ * not a power of two, and a negative hbm_budget or max_grid, with BASKER_ERR_INVALID. */
 
 /* Symbolic analysis of A (Sec. III-A bottleneck matching and strongly connected
  * components for the BTF, Alg. 2 fill order per block, Sec. III-C nested dissection

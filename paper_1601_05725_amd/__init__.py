@@ -36,7 +36,8 @@ class basker_options(ctypes.Structure):
                 ("btf", ctypes.c_int32), ("fill_order", ctypes.c_int32), ("nd_leaves", ctypes.c_int32),
                 ("nd_min_block", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("refactor_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("max_grid", ctypes.c_int32), ("hbm_budget", ctypes.c_int64), ("sched_flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class basker_info_t(ctypes.Structure):
@@ -50,7 +51,8 @@ class basker_info_t(ctypes.Structure):
                 ("refactor_fallbacks", ctypes.c_int32), ("pool_regrows", ctypes.c_int32),
                 ("nd_blocks", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("solve_levels", ctypes.c_int32),
                 ("crit_cols", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("reserved", ctypes.c_int32 * 9)]
+                ("dense_seps", ctypes.c_int32), ("sparse_seps", ctypes.c_int32),
+                ("device_bytes_plan", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

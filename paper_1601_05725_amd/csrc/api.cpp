@@ -17,12 +17,21 @@ using namespace basker;
 
 namespace {
 
-// device bytes are charged to the handle whose call is running on this thread
+// device bytes are charged to the handle whose call is running on this thread; an
+// allocation that would take the handle past its budget (0 = none) is refused
 thread_local int64_t* t_acct = nullptr;
+thread_local int64_t t_budget = 0;
 struct AcctScope {
   int64_t* prev;
-  explicit AcctScope(int64_t* a) : prev(t_acct) { t_acct = a; }
-  ~AcctScope() { t_acct = prev; }
+  int64_t prev_budget;
+  AcctScope(int64_t* a, int64_t budget) : prev(t_acct), prev_budget(t_budget) {
+    t_acct = a;
+    t_budget = budget;
+  }
+  ~AcctScope() {
+    t_acct = prev;
+    t_budget = prev_budget;
+  }
 };
 
 template <class T>
@@ -41,6 +50,7 @@ struct DBuf {
     if (n <= cap && p) return hipSuccess;
     release();
     int64_t m = n > 0 ? n : 1;
+    if (t_acct && t_budget > 0 && *t_acct + (int64_t)sizeof(T) * m > t_budget) return hipErrorOutOfMemory;
     hipError_t e = hipMalloc((void**)&p, sizeof(T) * (size_t)m);
     if (e != hipSuccess) { p = nullptr; return e; }
     cap = m;
@@ -137,7 +147,17 @@ extern "C" basker_status basker_default_options(basker_options* o) {
   o->device = 0;
   o->stream = nullptr;
   o->refactor_graph = 1;
+  o->max_grid = 0;
+  o->hbm_budget = 0;
+  o->sched_flags = 0;
   return BASKER_OK;
+}
+
+static bool options_valid(const basker_options& o) {
+  if (!(o.pivot_tol > 0.0 && o.pivot_tol <= 1.0)) return false;   // also rejects NaN
+  if (o.nd_leaves < 1 || (o.nd_leaves & (o.nd_leaves - 1)) != 0) return false;
+  if (o.hbm_budget < 0 || o.max_grid < 0) return false;
+  return true;
 }
 
 extern "C" const char* basker_status_string(basker_status s) {
@@ -157,10 +177,74 @@ extern "C" const char* basker_status_string(basker_status s) {
 
 extern "C" const char* basker_last_error(basker_handle h) { return h ? h->err.c_str() : ""; }
 
+// workgroups of the persistent factor launches: the widest level, capped by the
+// occupancy target and the caller's max_grid
+static int plan_grid(const Plan& P, const basker_options& o) {
+  const int nlev = (int)P.lvl_ptr.size() - 1;
+  int maxitems = 1;
+  for (int l = 0; l < nlev; l++) maxitems = std::max(maxitems, P.lvl_item_ptr[l + 1] - P.lvl_item_ptr[l]);
+  int grid = std::min(maxitems, kNumCu * kWavesPerCu);
+  if (o.max_grid > 0) grid = std::min(grid, o.max_grid);
+  return grid;
+}
+
+constexpr int kGwsSlots = 1 << 14;   // hash slots of a workgroup's global fallback workspace
+static int64_t gws_stride_bytes() { return ((48LL * kGwsSlots + 16 + 255) / 256) * 256; }
+
+// initial L/U pool entries: capacity_factor * nnz(diagonal blocks) + n
+static int64_t pool_capacity(const Plan& P, const basker_options& o) {
+  const double cf = o.capacity_factor > 0 ? o.capacity_factor : 6.0;
+  int64_t cap = (int64_t)(cf * (double)P.Ri.size()) + P.n + 64;
+  return std::min<int64_t>(cap, 0x7fffffffLL);
+}
+
+// separator columns and their entries bound the first-step buffer initially
+static int64_t cb_capacity(const Plan& P) {
+  const int64_t sepcols = P.lvl_col_ptr.back() - (P.lvl_col_ptr.size() > 1 ? P.lvl_col_ptr[1] : 0);
+  return std::max<int64_t>(4096, 256 * sepcols);
+}
+
+// Device bytes a handle holds after upload_plan, a factorization without pool growth
+// and a solve of 8 host right-hand sides: the same reservations, added up.
+static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
+  int64_t b = 0;
+  auto add = [&](size_t elem, int64_t cnt) { b += (int64_t)elem * std::max<int64_t>(cnt, 1); };
+  const int64_t n = P.n, nnzd = (int64_t)P.Ri.size(), nnzo = (int64_t)P.Oi.size();
+  const int64_t ns = (int64_t)P.seg_c0.size(), nitem = (int64_t)P.item_lo.size();
+  const int64_t nd = (int64_t)P.dsep_seg.size(), nr = (int64_t)P.dsep_rng_g0.size();
+  const int64_t nb = (int64_t)P.blkptr.size() - 1, ng = (int64_t)P.grpptr.size() - 1;
+  const int64_t nt = (int64_t)P.st_kind.size(), nlev = (int64_t)P.lvl_ptr.size() - 1;
+  add(4, n + 1); add(4, nnzd); add(4, nnzd);                       // Rp, Ri, Rmap
+  add(4, n); add(4, n);                                            // grp_lo, grp_hi
+  add(4, ns); add(4, ns); add(4, ns); add(4, nitem); add(4, nitem);  // segments, items
+  add(4, (int64_t)P.lvl_col.size());
+  add(4, nd); add(4, nd); add(4, nd + 1); add(4, nr); add(4, nr); add(4, nr);
+  add(8, nd); add(8, nd);
+  add(8, P.dsep_panel_total); add(8, P.dsep_bits_total);
+  add(4, n); add(4, n); add(4, n); add(4, n);                      // piv_local, cb_off/np/nn
+  const int64_t cb = cb_capacity(P);
+  add(4, cb); add(8, cb);
+  add(8, 2); add(4, 2 * nlev);
+  add(4, n + 1); add(4, nnzo); add(4, nnzo);                       // OTp, OTj, OTmap
+  add(4, n); add(4, n); add(4, nb + 1); add(4, ng + 1);            // prow, qcol, blkptr, grpptr
+  add(4, nt); add(4, nt); add(4, nt);
+  add(4, ng); add(4, ng + 1); add(4, (int64_t)P.sg_anc.size()); add(4, ng); add(8, ng); add(4, n); add(4, 1);
+  add(8, P.nnz); add(8, nnzd); add(8, nnzo);                       // vals, Rx, OTx
+  for (int t = 0; t < 6; t++) add(4, n);                           // pinv, piv, Lbeg..Ucnt
+  add(4, kStatusWords); add(8, 3);
+  const int64_t cap = pool_capacity(P, o);
+  add(4, cap); add(8, cap); add(4, cap); add(8, cap);
+  b += gws_stride_bytes() * plan_grid(P, o);
+  const int64_t nrhs = 8;
+  add(8, n * nrhs); add(8, n * nrhs); add(8, n * nrhs);            // W, Z, Bdev
+  add(8, P.s_gbuf_total * nrhs);
+  return b;
+}
+
 // Everything the device needs from the plan, plus the solve's row-wise coupling and
 // block dependency lists.
 static basker_status upload_plan(basker_ctx* h) {
-  AcctScope acct(&h->dev_bytes);
+  AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
   Plan& P = h->plan;
   const int n = P.n;
   hipStream_t s = h->stream;
@@ -208,13 +292,8 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->cb_off.reserve(n));
   HIPCHK(h, h->cb_np.reserve(n));
   HIPCHK(h, h->cb_nn.reserve(n));
-  {
-    // separator columns and their entries bound the first-step buffer initially
-    int64_t sepcols = P.lvl_col_ptr.back() - (P.lvl_col_ptr.size() > 1 ? P.lvl_col_ptr[1] : 0);
-    int64_t cb = std::max<int64_t>(4096, 256 * sepcols);
-    HIPCHK(h, h->cbI.reserve(cb));
-    HIPCHK(h, h->cbX.reserve(cb));
-  }
+  HIPCHK(h, h->cbI.reserve(cb_capacity(P)));
+  HIPCHK(h, h->cbX.reserve(cb_capacity(P)));
   HIPCHK(h, h->nnz_ctr.reserve(2));
   HIPCHK(h, h->lvl_ctr.reserve(std::max(2 * nlev, 1)));
   HIPCHK(h, h->OTp.upload(OTp, s));
@@ -260,24 +339,20 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->Lcnt.reserve(n));
   HIPCHK(h, h->Ubeg.reserve(n));
   HIPCHK(h, h->Ucnt.reserve(n));
-  HIPCHK(h, h->status.reserve(ST_WORDS));
+  HIPCHK(h, h->status.reserve(kStatusWords));
   HIPCHK(h, h->pool.reserve(3));
   (void)nb;
   // L/U pools
-  double cf = h->opt.capacity_factor > 0 ? h->opt.capacity_factor : 6.0;
-  int64_t cap = (int64_t)(cf * (double)nnzd) + n + 64;
-  if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+  const int64_t cap = pool_capacity(P, h->opt);
   HIPCHK(h, h->Li.reserve(cap));
   HIPCHK(h, h->Lx.reserve(cap));
   HIPCHK(h, h->Ui.reserve(cap));
   HIPCHK(h, h->Ux.reserve(cap));
   // persistent grid and the global fallback workspace (one region per workgroup)
-  int maxitems = 1;
-  for (int l = 0; l < nlev; l++) maxitems = std::max(maxitems, P.lvl_item_ptr[l + 1] - P.lvl_item_ptr[l]);
-  int grid = std::min(maxitems, kNumCu * kWavesPerCu);
+  const int grid = plan_grid(P, h->opt);
   h->grid = grid;
-  h->gws_slots = 1 << 14;
-  h->gws_stride = ((48LL * h->gws_slots + 16 + 255) / 256) * 256;
+  h->gws_slots = kGwsSlots;
+  h->gws_stride = gws_stride_bytes();
   HIPCHK(h, h->gws.reserve(h->gws_stride * grid));
   HIPCHK(h, hipMemsetAsync(h->gws.p, 0xff, (size_t)(h->gws_stride * grid), s));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -290,6 +365,10 @@ static basker_status make_handle(const basker_options* o, basker_handle* out, ba
   basker_ctx* h = new (std::nothrow) basker_ctx();
   if (!h) return BASKER_ERR_OOM;
   if (o) h->opt = *o; else basker_default_options(&h->opt);
+  if (!options_valid(h->opt)) {
+    delete h;
+    return BASKER_ERR_INVALID;
+  }
   h->device = h->opt.device;
   if (h->device < 0) {  // analysis only: no device work
     *ph = h;
@@ -329,6 +408,14 @@ static void fill_info_static(basker_ctx* h) {
   I.nlevels = (int32_t)P.lvl_ptr.size() - 1;
   I.solve_levels = (int32_t)P.st_lvl_ptr.size() - 1;
   I.fail_col = -1;
+  I.sparse_seps = 0;
+  {
+    std::vector<char> dense(P.seg_c0.size(), 0);
+    for (int32_t sg : P.dsep_seg) dense[sg] = 1;
+    for (size_t sg = 0; sg < P.seg_c0.size(); sg++)
+      if (P.seg_level[sg] >= 1 && !dense[sg]) I.sparse_seps++;
+  }
+  I.device_bytes_plan = plan_device_bytes(P, h->opt);
 }
 
 extern "C" basker_status basker_symbolic(int32_t n, const int32_t* colptr, const int32_t* rowind, const double* values,
@@ -408,6 +495,7 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.diag_pref = h->opt.diag_pref;
   a.refactor = refactor;
   a.gws = h->gws.p; a.gws_stride = h->gws_stride; a.gws_slots = h->gws_slots;
+  a.reverse = h->opt.sched_flags & 1;
   return a;
 }
 
@@ -467,6 +555,7 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     if (grid > 0 && (e = launch_factor_sep_step1(a, grid, s)) != hipSuccess) return e;
     a.level = l;
     grid = std::min(a.item_end - a.item_begin, kNumCu * 3);
+    if (h->opt.max_grid > 0) grid = std::min(grid, h->opt.max_grid);
     if (grid > 0) {
       if (refactor) {
         a.mode = 0;
@@ -558,6 +647,7 @@ static basker_status do_factor(basker_ctx* h) {
       h->info.lnz = h->lnz;
       h->info.unz = h->unz;
       h->info.offdiag_pivots = st[ST_OFFDIAG];
+      h->info.dense_seps = st[ST_DSEP];
       h->factored = true;
       h->info.factor_calls++;
       return BASKER_OK;
@@ -595,7 +685,7 @@ static basker_status do_factor(basker_ctx* h) {
 
 extern "C" basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device) {
   if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
-  AcctScope acct(&h->dev_bytes);
+  AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   HIPCHK(h, hipSetDevice(h->device));
   basker_status r = stage_values(h, values, values_on_device);
@@ -605,7 +695,7 @@ extern "C" basker_status basker_factor(basker_handle h, const double* values, in
 
 extern "C" basker_status basker_refactor(basker_handle h, const double* values, int32_t values_on_device) {
   if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
-  AcctScope acct(&h->dev_bytes);
+  AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "refactor before a successful factor");
   HIPCHK(h, hipSetDevice(h->device));
@@ -651,7 +741,7 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
 
 extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb, int32_t B_on_device) {
   if (!h || nrhs < 0 || (nrhs > 0 && !B) || ldb < h->plan.n) return BASKER_ERR_INVALID;
-  AcctScope acct(&h->dev_bytes);
+  AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
   if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "solve before a successful factor");
   if (nrhs == 0 || h->plan.n == 0) return BASKER_OK;
   HIPCHK(h, hipSetDevice(h->device));

@@ -25,8 +25,11 @@ constexpr int kWavesPerCu = 6;        // persistent-grid occupancy target
 constexpr int kNumCu = 256;
 
 // status words (device): [0] error code, [1] failing column (min), [2] pool overflow,
-// [3] workspace overflow, [4] pivots off the diagonal
-enum { ST_CODE = 0, ST_FAILCOL = 1, ST_POOL = 2, ST_WS = 3, ST_OFFDIAG = 4, ST_CBPOOL = 5, ST_WORDS = 8 };
+// [3] workspace overflow, [4] pivots off the diagonal, [5] separator buffer overflow,
+// [6] separators completed by the dense kernel
+enum { ST_CODE = 0, ST_FAILCOL = 1, ST_POOL = 2, ST_WS = 3, ST_OFFDIAG = 4, ST_CBPOOL = 5, ST_DSEP = 6,
+       ST_WORDS = 8 };
+constexpr int kStatusWords = ST_WORDS;
 enum { DEV_OK = 0, DEV_SINGULAR = 3, DEV_REFACTOR_FAIL = 8, DEV_WORKSPACE = 7, DEV_POOL = 4, DEV_PATTERN = 5,
        DEV_STALL = 9 };
 
@@ -84,6 +87,7 @@ struct FactorArgs {
   char* gws;               // global fallback workspace, one region per workgroup
   int64_t gws_stride;      // bytes per region
   int32_t gws_slots;       // hash slots per region (power of two)
+  int32_t reverse;         // hand out work items last first (results do not depend on it)
 };
 
 struct SolveArgs {

@@ -780,7 +780,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
       idx = __shfl(idx, 0, 64);
       if (idx >= ncols) break;
       if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
-      const int k = a.col_list[a.col_begin + idx];
+      const int k = a.col_list[a.col_begin + (a.reverse ? ncols - 1 - idx : idx)];
       int rc = factor_column(a, wl, k, al, pre, -1);
       if (rc == 1) {
         rc = factor_column(a, wg, k, al, pre, -1);
@@ -800,7 +800,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
       idx = __shfl(idx, 0, 64);
       if (idx >= nitems) break;
       if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
-      const int it = a.item_begin + idx;
+      const int it = a.item_begin + (a.reverse ? nitems - 1 - idx : idx);
       for (int q = a.item_lo[it]; q < a.item_hi[it]; q++) {
         const int sg = a.lvl_seg[q];
         const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];

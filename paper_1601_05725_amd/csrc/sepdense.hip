@@ -127,7 +127,10 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
       int bi = 0x7fffffff;
       for (int t = 0; t < nw; t++)
         if (red_v[t] > bm || (red_v[t] == bm && red_i[t] < bi)) { bm = red_v[t]; bi = red_i[t]; }
-      const bool dcand = !((piv_bits[k >> 6] >> (k & 63)) & 1ull);
+      // candidates are the structural, non-pivotal rows of the separator; a structurally
+      // zero row holds an exact 0 in the panel, so it can only attain the maximum when the
+      // column is singular, but the diagonal test must see its structure explicitly
+      const bool dcand = !((piv_bits[k >> 6] >> (k & 63)) & 1ull) && ((Sk[k >> 6] >> (k & 63)) & 1ull);
       int p;
       int fail = 0;
       if (!a.refactor) {
@@ -135,7 +138,8 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
         p = (a.diag_pref && dcand && fabs(Pk[k]) >= a.tau * bm) ? k : bi;
       } else {
         p = a.piv[c] - c0;
-        const bool okp = p >= 0 && p < m && !((piv_bits[p >> 6] >> (p & 63)) & 1ull);
+        const bool okp = p >= 0 && p < m && !((piv_bits[p >> 6] >> (p & 63)) & 1ull) &&
+                         ((Sk[p >> 6] >> (p & 63)) & 1ull);
         if (!(okp && (bm > 0.0) && Pk[p] != 0.0 && fabs(Pk[p]) >= a.tau * bm)) fail = DEV_REFACTOR_FAIL;
       }
       if (fail) {
@@ -348,6 +352,7 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
     __syncthreads();
   }
   if (wv == 0 && lane == 0) {
+    atomicAdd(&a.status[ST_DSEP], 1);
     if (offdiag) atomicAdd(&a.status[ST_OFFDIAG], offdiag);
     if (!a.refactor) {
       atomicAdd(&a.nnz_ctr[0], (unsigned long long)lnz);

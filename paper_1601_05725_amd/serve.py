@@ -90,16 +90,31 @@ class _State:
         self.cur: Optional[np.ndarray] = None
 
 
+def library_estimate(p: Pattern) -> int:
+    """Device bytes a handle of pattern p will hold after its first factorization and a
+    solve with up to 8 right-hand sides, as the library computes them from its own
+    plan (a host-only symbolic analysis: no device memory is touched)."""
+    h = Handle.symbolic(_Csc(p), default_options(**dict(p.options, device=-1)))
+    try:
+        return int(h.info()["device_bytes_plan"])
+    finally:
+        h.free()
+
+
 class Server:
     """slots: concurrent requests; hbm_budget: bytes of device memory the resident
-    handles may hold (a new handle is estimated before it is admitted)."""
+    handles may hold.  A pattern not yet resident is admitted on its estimate (by
+    default the library's own, from a host-only analysis, computed once per pattern);
+    once it has run, its handle's actual device bytes count instead."""
 
     def __init__(self, patterns: list, slots: int = 8, hbm_budget: int = 200 << 30,
                  estimate: Optional[Callable[[Pattern], int]] = None):
         self.patterns = {p.key: p for p in patterns}
         self.slots = slots
         self.budget = hbm_budget
-        self.estimate = estimate or (lambda p: 64 * int(p.colptr[-1]) + 256 * p.n + (8 << 20))
+        self._est_fn = estimate or library_estimate
+        self._est_cache: dict = {}
+        self.peak_bytes = 0
         self.resident: dict = {}
         self.state = {p.key: _State() for p in patterns}
         self.restores = 0
@@ -132,6 +147,11 @@ class Server:
             if r.handle is not None:
                 r.handle.free()
         self.resident.clear()
+
+    def estimate(self, p: Pattern) -> int:
+        if p.key not in self._est_cache:
+            self._est_cache[p.key] = int(self._est_fn(p))
+        return self._est_cache[p.key]
 
     def resident_bytes(self) -> int:
         return sum(r.bytes for r in self.resident.values())
@@ -211,6 +231,7 @@ class Server:
                     r.busy = False
                     r.last_use = req.done
                     self.completed += 1
+                    self.peak_bytes = max(self.peak_bytes, self.resident_bytes())
                     self.cv.notify_all()
                 req.event.set()
 

@@ -200,3 +200,38 @@ def test_ordered_symbolic_validation(bk):
     bad[0] = 1
     with pytest.raises(bk.BaskerError):
         bk.Handle.symbolic_ordered(a, bad, r, [0, n], [0, n], bk.default_options(device=-1))
+
+
+@pytest.mark.parametrize("field,value", [("pivot_tol", 0.0), ("pivot_tol", -1e-3), ("pivot_tol", 1.5),
+                                         ("pivot_tol", float("nan")), ("nd_leaves", 3), ("nd_leaves", 0),
+                                         ("hbm_budget", -1), ("max_grid", -2)])
+def test_options_rejected(bk, field, value):
+    """Options outside their documented ranges are refused before any analysis."""
+    a = synth.gen_mna(200, seed=3)
+    with pytest.raises(bk.BaskerError) as e:
+        analyse(bk, a, **{field: value})
+    assert e.value.status == bk.ERR_INVALID
+
+
+def test_options_struct_layout(bk):
+    """The binding's structs match the header: offsets of the fields after the pointer."""
+    import ctypes
+    o = bk.basker_options
+    assert ctypes.sizeof(o) == 88
+    assert o.stream.offset == 48 and o.refactor_graph.offset == 56 and o.max_grid.offset == 60
+    assert o.hbm_budget.offset == 64 and o.sched_flags.offset == 72
+    assert bk.basker_info_t.device_bytes_plan.offset % 8 == 0
+
+
+def test_device_bytes_plan_estimate(bk):
+    """The host-only analysis reports the device memory a handle will hold: at least the
+    L/U pools (capacity_factor * nnz(diagonal blocks) entries of 4 + 8 bytes, twice),
+    the value arrays and the solve vectors for 8 right-hand sides."""
+    a = synth.gen_mna(3000, seed=5)
+    for cf in (2.0, 6.0):
+        inf = analyse(bk, a, capacity_factor=cf).info()
+        pools = 2 * 12 * int(cf * inf["nnz_diag"])
+        assert inf["device_bytes_plan"] >= pools + 8 * a.nnz + 3 * 8 * 8 * a.n
+    small = analyse(bk, a, capacity_factor=2.0).info()["device_bytes_plan"]
+    big = analyse(bk, a, capacity_factor=6.0).info()["device_bytes_plan"]
+    assert big - small >= 2 * 12 * int(4.0 * analyse(bk, a).info()["nnz_diag"]) - 64

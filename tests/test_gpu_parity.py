@@ -169,10 +169,22 @@ def test_c0_full_pipeline(bk, orc):
     say("C0 info %s" % {k: inf[k] for k in ("nblocks", "lnz", "unz", "max_depth", "factor_kernel_ms", "offdiag_pivots")})
 
 
+def nd_separator_groups(h):
+    """Groups that are ND separators (some group names them as parent)."""
+    gpar = h.group_tree()
+    return set(int(g) for g in gpar[gpar >= 0])
+
+
 def test_nd_block(bk, orc):
     a = synth.gen_mna(12000, seed=6)
     h, order, ext = run_case(bk, orc, a, label="mna12k-nd", nd_min_block=3000, nd_leaves=8)
-    assert h.info()["nd_blocks"] >= 1
+    inf = h.info()
+    assert inf["nd_blocks"] >= 1
+    # both separator paths ran: the dense kernel counts the separators it completed
+    seps = nd_separator_groups(h)
+    say("separators %d: dense %d sparse %d" % (len(seps), inf["dense_seps"], inf["sparse_seps"]))
+    assert inf["dense_seps"] > 0 and inf["sparse_seps"] > 0
+    assert inf["dense_seps"] + inf["sparse_seps"] == len(seps)
 
 
 def test_large_block_without_nd(bk, orc):
@@ -313,3 +325,128 @@ def test_device_pointers(bk, orc):
     torch.cuda.synchronize()
     x = Bt.cpu().numpy().T
     assert orc.residual(a, x, b) <= RES_TOL
+
+
+
+# ---------------------------------------------------------------------------
+# exact ties, full-size parity, determinism, refactor on ND blocks
+# ---------------------------------------------------------------------------
+
+def integer_matrix(n, density, seed):
+    """{-1, 0, 1} entries with a +-1 diagonal: magnitudes tie exactly, so the pivot
+    choices exercise the smallest-index tie-break and the threshold equality."""
+    s = synth.Stream(synth.substream_key(seed, 5))
+    D = s.integers(-1, 2, n * n).astype(float).reshape(n, n)
+    D[s.uniform(n * n).reshape(n, n) >= density] = 0.0
+    D[np.arange(n), np.arange(n)] = np.where(s.uniform(n) < 0.5, 1.0, -1.0)
+    return D
+
+
+@pytest.mark.parametrize("tau,dp", [(1.0, 0), (1.0, 1), (0.5, 1)])
+@pytest.mark.parametrize("n,density,seed", [(12, 1.0, 20), (12, 1.0, 24), (160, 0.03, 22), (400, 0.012, 23)])
+def test_exact_ties_integer(bk, orc, tau, dp, n, density, seed):
+    a = synth.csc_from_dense(integer_matrix(n, density, seed))
+    order = orc.Ordering.natural(n)
+    f = orc.factor(a, order, tau=tau, diag_pref=bool(dp), update_order=orc.ORDER_ASCENDING)
+    if f.status != 0:
+        pytest.skip("singular draw")
+    assert np.count_nonzero(f.margin == 0.0) > 0     # the case really holds exact ties
+    run_case(bk, orc, a, order, tau=tau, diag_pref=dp, label="ties-%d-%d" % (n, seed), nrhs=1)
+
+
+def test_full_c2_bitwise(bk, orc):
+    """The batched-BTF workload at full size (50,000 blocks + the 100k ND block, 16
+    leaves, n = 346,411), as the benchmark factors it: pivots, patterns and values bit
+    for bit against the oracle, dense separators included; solve residual."""
+    inp = synth.gen_batched_btf()
+    a = inp.a
+    say("C2 full n=%d nnz=%d" % (a.n, a.nnz))
+    h = bk.Handle.symbolic(a, bk.default_options(nd_leaves=16))
+    prow, qcol, bp, gp = h.ordering()
+    order = orc.Ordering(prow, qcol, bp, gp)
+    h.factor(a.values)
+    ext = h.extract()
+    f = orc.factor(a, order, update_order=orc.ORDER_ASCENDING)
+    assert f.status == 0
+    compare_exact(ext, f)
+    inf = h.info()
+    say("C2 dense separators %d sparse %d offdiag pivots %d" % (inf["dense_seps"], inf["sparse_seps"],
+                                                                inf["offdiag_pivots"]))
+    assert inf["dense_seps"] > 0
+    b = synth.rhs(a.n, 1)
+    x = h.solve(b)
+    assert orc.residual(a, x, b) <= RES_TOL
+
+
+@pytest.mark.parametrize("max_grid,flags", [(1, 0), (37, 1), (0, 1)])
+def test_deterministic_under_schedule(bk, orc, max_grid, flags):
+    """Survey T12: other grid sizes and the reverse order of work items change which
+    workgroup factors what and when; the factors must not change by a bit."""
+    inp = synth.gen_batched_btf(nblocks=300, big=4000, seed=7)
+    a = inp.a
+    h0 = bk.Handle.symbolic(a, bk.default_options(nd_min_block=2000, nd_leaves=4))
+    h0.factor(a.values)
+    e0 = h0.extract()
+    h1 = bk.Handle.symbolic(a, bk.default_options(nd_min_block=2000, nd_leaves=4, max_grid=max_grid,
+                                                  sched_flags=flags))
+    h1.factor(a.values)
+    e1 = h1.extract()
+    for x, y in ((e0.piv, e1.piv), (e0.Lp, e1.Lp), (e0.Li, e1.Li), (e0.Lx, e1.Lx), (e0.Up, e1.Up),
+                 (e0.Ui, e1.Ui), (e0.Ux, e1.Ux)):
+        np.testing.assert_array_equal(x, y)
+    b = synth.rhs(a.n, 2)
+    np.testing.assert_array_equal(h0.solve(b), h1.solve(b))
+
+
+def test_refactor_nd_block_vs_oracle(bk, orc):
+    """Refactorization on an ND block with dense and sparse separators (the known-pattern
+    separator first step, known-pattern columns at separator levels and the dense
+    kernel in refactor mode) against the oracle's refactorization, step by step; steps
+    whose threshold check fails fall back and match the oracle's full factorization."""
+    a = synth.gen_mna(12000, seed=6)
+    h = bk.Handle.symbolic(a, bk.default_options(nd_min_block=3000, nd_leaves=8))
+    prow, qcol, bp, gp = h.ordering()
+    order = orc.Ordering(prow, qcol, bp, gp)
+    h.factor(a.values)
+    assert h.info()["dense_seps"] > 0
+    base = h.extract()
+    assert h.refactor(a.values) == bk.OK
+    compare_exact(h.extract(), orc.refactor(a, order, base.piv, update_order=orc.ORDER_ASCENDING))
+    passed = fell = 0
+    for t, vals in enumerate(synth.value_sequence(a, 6, sigma=0.002)):
+        say("nd refactor step %d" % t)
+        at = a.with_values(vals)
+        st = h.refactor(vals)
+        ref = orc.refactor(at, order, base.piv, update_order=orc.ORDER_ASCENDING)
+        if ref.status == 0:
+            assert st == bk.OK
+            compare_exact(h.extract(), ref)
+            passed += 1
+        else:
+            assert st == bk.REFACTOR_FELL_BACK
+            compare_exact(h.extract(), orc.factor(at, order, update_order=orc.ORDER_ASCENDING))
+            base = h.extract()
+            fell += 1
+    say("nd refactor passed %d fell back %d" % (passed, fell))
+    assert passed >= 1
+
+
+def test_hbm_budget_and_estimate(bk, orc):
+    """The handle's device memory after a factorization and an 8-RHS solve matches the
+    analysis estimate; a budget below it refuses the analysis with BASKER_ERR_OOM, one
+    above it holds."""
+    a = synth.gen_mna(5000, seed=13)
+    est = bk.Handle.symbolic(a, bk.default_options(device=-1)).info()["device_bytes_plan"]
+    h = bk.Handle.symbolic(a, bk.default_options(hbm_budget=est + (1 << 20)))
+    h.factor(a.values)
+    b = synth.rhs(a.n, 8)
+    x = h.solve(b)
+    inf = h.info()
+    say("estimate %d held %d regrows %d" % (est, inf["device_bytes"], inf["pool_regrows"]))
+    assert inf["pool_regrows"] == 0
+    assert 0.9 * est <= inf["device_bytes"] <= est
+    assert orc.residual(a, x, b) <= RES_TOL
+    h.free()
+    with pytest.raises(bk.BaskerError) as e:
+        bk.Handle.symbolic(a, bk.default_options(hbm_budget=est // 2))
+    assert e.value.status == bk.ERR_OOM

@@ -81,3 +81,29 @@ def test_served_results_equal_sequential(bk, budget_mb):
             np.testing.assert_array_equal(a.result, b.result)
     if budget_mb < 100:
         assert evictions > 0 and restores > 0
+
+
+def test_admission_budget_binds_with_library_estimate(bk):
+    """Default admission (the library's own device-byte estimate): with a budget that
+    holds only about two of the patterns, the resident handles' actual device bytes
+    never exceed it, handles are evicted, and every result still equals the
+    one-at-a-time path."""
+    from paper_1601_05725_amd import serve
+    pats, reqs = make_stream(serve, seed=23, nreq=40)
+    est = {p.key: serve.library_estimate(p) for p in pats}
+    say("estimates MB %s" % {k: round(v / 2**20, 1) for k, v in est.items()})
+    budget = 2 * max(est.values()) + 1
+    seq = serve.run_sequential(pats, clone(serve, reqs))
+    srv = serve.Server(pats, slots=4, hbm_budget=budget)
+    mine = [srv.submit(r) for r in clone(serve, reqs)]
+    for r in mine:
+        assert r.event.wait(120), "request did not finish"
+    peak, evictions = srv.peak_bytes, srv.evictions
+    srv.close()
+    say("budget %d peak %d evictions %d" % (budget, peak, evictions))
+    assert peak <= budget
+    assert evictions > 0
+    for a, b in zip(seq, mine):
+        assert b.error is None, b.error
+        if a.kind == serve.SOLVE:
+            np.testing.assert_array_equal(a.result, b.result)
