@@ -150,6 +150,17 @@ basker_status basker_refactor(basker_handle h, const double* values, int32_t val
  * host pointer, or a device pointer when B_on_device != 0. */
 basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb, int32_t B_on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): basker_solve on a device-resident B
+ * (column-major, leading dimension ldb >= n) that calls no allocating routine.  Its
+ * work vectors live in a static device array of 4,194,304 doubles (32 MiB), which
+ * every GPU the library runs on holds until the process ends; a solve needing more
+ * than (2 n + the ND node buffers) * nrhs of them fails with BASKER_ERR_WORKSPACE
+ * before any device work.  Calls on one GPU share that array, so calls that overlap
+ * on one GPU (different handles, streams or threads) race and must be serialised by
+ * the caller.  Same kernels and results as basker_solve. */
+basker_status basker_solve_noalloc(basker_handle h, int32_t nrhs, double* B, int32_t ldb);
+
 /* Counters and timings of the handle. */
 basker_status basker_info(basker_handle h, basker_info_t* info);
 

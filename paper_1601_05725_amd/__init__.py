@@ -27,7 +27,7 @@ ERR_DEVICE = -6
 ERR_WORKSPACE = -7
 
 EXPORTED = ["basker_default_options", "basker_symbolic", "basker_symbolic_ordered", "basker_factor",
-            "basker_refactor", "basker_solve", "basker_info", "basker_get_ordering", "basker_extract",
+            "basker_refactor", "basker_solve", "basker_solve_noalloc", "basker_info", "basker_get_ordering", "basker_extract",
             "basker_free", "basker_status_string", "basker_last_error"]
 
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.basker_refactor.argtypes = [P, P, i32]
     lib.basker_solve.restype = i32
     lib.basker_solve.argtypes = [P, i32, P, i32, i32]
+    lib.basker_solve_noalloc.restype = i32
+    lib.basker_solve_noalloc.argtypes = [P, i32, P, i32]
     lib.basker_info.restype = i32
     lib.basker_info.argtypes = [P, ctypes.POINTER(basker_info_t)]
     lib.basker_get_ordering.restype = i32
@@ -211,6 +213,17 @@ class Handle:
             B = B.reshape(-1, 1, order="F")
         self._check(load().basker_solve(self._h, B.shape[1], _np_ptr(B), B.shape[0], 0))
         return B[:, 0] if vec else B
+
+    def solve_noalloc(self, b):
+        """Solve a float64 device tensor in place through the entry point that allocates
+        nothing (a (nrhs, n) contiguous tensor holds the n x nrhs column-major B)."""
+        if not (hasattr(b, "data_ptr") and getattr(b, "is_cuda", False)):
+            raise TypeError("solve_noalloc takes a device tensor")
+        if not b.is_contiguous() or str(b.dtype) != "torch.float64":
+            raise ValueError("B must be a contiguous float64 tensor")
+        nrhs, ld = (1, b.shape[0]) if b.dim() == 1 else (b.shape[0], b.shape[1])
+        self._check(load().basker_solve_noalloc(self._h, nrhs, ctypes.c_void_p(b.data_ptr()), ld))
+        return b
 
     # -- queries -----------------------------------------------------------
     def info(self) -> dict:

@@ -739,6 +739,56 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
   return fail(h, BASKER_ERR_DEVICE, "refactor kernel status " + std::to_string(st[ST_CODE]));
 }
 
+// The task launches of one solve on device-resident B (leading dimension ld) with the
+// work vectors W, Z (n * nrhs doubles each) and the ND node buffers gbuf
+// (s_gbuf_total * nrhs doubles) given by the caller; the status word is the
+// handle's.  Enqueues only: allocates nothing.
+static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int32_t ld, double* W, double* Z,
+                                   double* gbuf) {
+  hipStream_t s = h->stream;
+  SolveArgs a{};
+  a.n = h->plan.n;
+  a.nrhs = nrhs;
+  a.ldb = ld;
+  a.blkptr = h->blkptr.p;
+  a.grpptr = h->grpptr.p;
+  a.st_kind = h->st_kind.p; a.st_id = h->st_id.p; a.st_need = h->st_need.p;
+  a.sg_fd = h->sg_fd.p; a.sg_anc_ptr = h->sg_anc_ptr.p; a.sg_anc = h->sg_anc.p;
+  a.sg_choff = h->sg_choff.p; a.sg_tbase = h->sg_tbase.p; a.rowpos = h->s_rowpos.p;
+  a.gbuf_total = h->plan.s_gbuf_total;
+  a.gbuf = gbuf;
+  a.piv = h->piv.p;
+  a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Li = h->Li.p; a.Lx = h->Lx.p;
+  a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
+  a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
+  a.prow = h->prow.p; a.qcol = h->qcol.p;
+  a.B = dB; a.W = W; a.Z = Z;
+  a.status = h->s_status.p;
+  const Plan& P = h->plan;
+  const int nsl = (int)P.st_lvl_ptr.size() - 1;
+  HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 1, s));
+  HIPCHK(h, hipEventRecord(h->ev[2], s));
+  for (int l = 0; l < nsl; l++) {
+    a.t_begin = P.st_lvl_ptr[l];
+    a.lds_doubles = h->st_lvl_lds[l];
+    HIPCHK(h, launch_solve_tasks(a, P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l], s));
+  }
+  HIPCHK(h, launch_solve_finish(a, s));
+  HIPCHK(h, hipEventRecord(h->ev[3], s));
+  return BASKER_OK;
+}
+
+// wait for the solve just enqueued, read its status word and timing
+static basker_status finish_solve(basker_ctx* h) {
+  int32_t sst = 0;
+  HIPCHK(h, hipMemcpyAsync(&sst, h->s_status.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev[2], h->ev[3]) == hipSuccess) h->info.solve_kernel_ms = ms;
+  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve: factor entry outside its block or ND node rows");
+  return BASKER_OK;
+}
+
 extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb, int32_t B_on_device) {
   if (!h || nrhs < 0 || (nrhs > 0 && !B) || ldb < h->plan.n) return BASKER_ERR_INVALID;
   AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
@@ -760,45 +810,31 @@ extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, 
     ld = n;
   }
   HIPCHK(h, h->gbuf.reserve(std::max<int64_t>(h->plan.s_gbuf_total * nrhs, 1)));
-  SolveArgs a{};
-  a.n = n;
-  a.nrhs = nrhs;
-  a.ldb = ld;
-  a.blkptr = h->blkptr.p;
-  a.grpptr = h->grpptr.p;
-  a.st_kind = h->st_kind.p; a.st_id = h->st_id.p; a.st_need = h->st_need.p;
-  a.sg_fd = h->sg_fd.p; a.sg_anc_ptr = h->sg_anc_ptr.p; a.sg_anc = h->sg_anc.p;
-  a.sg_choff = h->sg_choff.p; a.sg_tbase = h->sg_tbase.p; a.rowpos = h->s_rowpos.p;
-  a.gbuf_total = h->plan.s_gbuf_total;
-  a.gbuf = h->gbuf.p;
-  a.piv = h->piv.p;
-  a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Li = h->Li.p; a.Lx = h->Lx.p;
-  a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
-  a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
-  a.prow = h->prow.p; a.qcol = h->qcol.p;
-  a.B = dB; a.W = h->W.p; a.Z = h->Z.p;
-  a.status = h->s_status.p;
-  const Plan& P = h->plan;
-  const int nsl = (int)P.st_lvl_ptr.size() - 1;
-  HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 1, s));
-  HIPCHK(h, hipEventRecord(h->ev[2], s));
-  for (int l = 0; l < nsl; l++) {
-    a.t_begin = P.st_lvl_ptr[l];
-    a.lds_doubles = h->st_lvl_lds[l];
-    HIPCHK(h, launch_solve_tasks(a, P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l], s));
-  }
-  HIPCHK(h, launch_solve_finish(a, s));
-  HIPCHK(h, hipEventRecord(h->ev[3], s));
+  basker_status r = enqueue_solve(h, nrhs, dB, ld, h->W.p, h->Z.p, h->gbuf.p);
+  if (r != BASKER_OK) return r;
   if (!B_on_device)
     HIPCHK(h, hipMemcpy2DAsync(B, sizeof(double) * (size_t)ldb, h->Bdev.p, sizeof(double) * n, sizeof(double) * n,
                                nrhs, hipMemcpyDeviceToHost, s));
-  int32_t sst = 0;
-  HIPCHK(h, hipMemcpyAsync(&sst, h->s_status.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(h, hipStreamSynchronize(s));
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, h->ev[2], h->ev[3]) == hipSuccess) h->info.solve_kernel_ms = ms;
-  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve: factor entry outside its block or ND node rows");
-  return BASKER_OK;
+  return finish_solve(h);
+}
+
+extern "C" basker_status basker_solve_noalloc(basker_handle h, int32_t nrhs, double* B, int32_t ldb) {
+  if (!h || nrhs < 0 || (nrhs > 0 && !B) || ldb < h->plan.n) return BASKER_ERR_INVALID;
+  if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
+  if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "solve before a successful factor");
+  if (nrhs == 0 || h->plan.n == 0) return BASKER_OK;
+  HIPCHK(h, hipSetDevice(h->device));
+  double* sp = nullptr;
+  HIPCHK(h, noalloc_scratch(h->device, &sp));
+  const int64_t n = h->plan.n;
+  const int64_t need = (2 * n + h->plan.s_gbuf_total) * (int64_t)nrhs;
+  if (need > kNoAllocScratchDoubles)
+    return fail(h, BASKER_ERR_WORKSPACE,
+                "solve needs " + std::to_string(need) + " doubles of scratch (2 n + ND buffers, times nrhs); the "
+                "static scratch holds " + std::to_string(kNoAllocScratchDoubles));
+  basker_status r = enqueue_solve(h, nrhs, B, ldb, sp, sp + n * nrhs, sp + 2 * n * nrhs);
+  if (r != BASKER_OK) return r;
+  return finish_solve(h);
 }
 
 extern "C" basker_status basker_info(basker_handle h, basker_info_t* info) {

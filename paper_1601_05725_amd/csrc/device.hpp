@@ -169,5 +169,9 @@ size_t solve_lds_bytes(int32_t work_doubles);
 hipError_t solve_lds_setup(size_t max_bytes);
 hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s);
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s);
+// the static device scratch of the solve that allocates nothing: its size in doubles,
+// and its address on a device (looked up once per device; the device must be current)
+constexpr int64_t kNoAllocScratchDoubles = 4ll << 20;
+hipError_t noalloc_scratch(int device, double** ptr);
 
 }  // namespace basker

@@ -17,7 +17,16 @@
 // column in a fixed order, so results do not depend on scheduling.
 #include "device.hpp"
 
+#include <map>
+#include <mutex>
+
 namespace basker {
+
+// Work vectors of basker_solve_noalloc: W, Z and the ND node buffers of one solve.
+// Every device the library runs on holds its own copy until the process ends.  Host
+// code never uses this name as an address: noalloc_scratch looks the device address
+// up once per device and every launch takes that pointer.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
 
 namespace {
 
@@ -363,6 +372,22 @@ hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s) {
   if (ntasks > 0)
     hipLaunchKernelGGL(solve_task_kernel, dim3(ntasks), dim3(64), solve_lds_bytes(a.lds_doubles), s, a);
   return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(int device, double** ptr) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    double* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    it = addr.emplace(device, p).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s) {
