@@ -60,7 +60,10 @@ typedef struct {
   int32_t fill_order;      /* minimum-degree order inside blocks (default 1) */
   int32_t nd_leaves;       /* leaves of the ND tree of large blocks, power of two (default 16) */
   int32_t nd_min_block;    /* blocks of at least this order use ND (default 10000) */
-  double capacity_factor;  /* initial L/U pool = factor * nnz(diagonal blocks) (default 6; grows on overflow) */
+  double capacity_factor;  /* initial L/U pools: 0 (default) = twice the fill of a factorization
+                              without row exchanges, counted by the symbolic analysis (6 * nnz of
+                              the diagonal blocks if that count exceeds its work budget);
+                              > 0 = this factor * nnz(diagonal blocks).  Pools grow on overflow */
   int32_t device;          /* HIP device ordinal (default 0); -1 = symbolic analysis only, no device work */
   void* stream;            /* hipStream_t to enqueue on; NULL = the handle's own stream */
   int32_t refactor_graph;  /* 1 (default): basker_refactor replays a HIP graph of its launches,
@@ -71,8 +74,13 @@ typedef struct {
   int64_t hbm_budget;      /* bytes of device memory the handle may hold (0 = unlimited): an
                               allocation beyond it fails the call with BASKER_ERR_OOM */
   int32_t sched_flags;     /* bit 0: hand out the work items of every level in reverse order;
-                              results do not depend on it (a check of determinism) */
-  int32_t reserved[3];
+                              bit 1: no speculative schedule of the first level (every
+                              column waits for its column-elimination-tree children);
+                              results do not depend on either (checks of determinism) */
+  int32_t item_cols;       /* first-level work items hold at least this many columns unless a
+                              block or ND leaf is larger (0 = 256) */
+  int32_t coop_waves;      /* wavefronts per workgroup of the first level: 4, 6 or 8 (0 = 6) */
+  int32_t reserved[1];
 } basker_options;
 
 typedef struct {
@@ -107,7 +115,11 @@ typedef struct {
                                 factorization and a solve with 8 right-hand sides (set by the
                                 symbolic analysis, also for device = -1; pool growth on an
                                 underestimated fill adds to it) */
-  int32_t reserved[8];
+  int32_t coop_items;        /* work items of the first level (cooperative workgroups; 0 = not used) */
+  int32_t coop_waves;        /* wavefronts per first-level workgroup */
+  int32_t redo_items;        /* first-level items the last factorization redid after a failed speculation */
+  int32_t learn_events;      /* factorizations whose observed dependencies were merged into the schedule */
+  int32_t reserved[4];
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */

@@ -37,7 +37,7 @@ class basker_options(ctypes.Structure):
                 ("nd_min_block", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("refactor_graph", ctypes.c_int32),
                 ("max_grid", ctypes.c_int32), ("hbm_budget", ctypes.c_int64), ("sched_flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("item_cols", ctypes.c_int32), ("coop_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class basker_info_t(ctypes.Structure):
@@ -52,7 +52,9 @@ class basker_info_t(ctypes.Structure):
                 ("nd_blocks", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("solve_levels", ctypes.c_int32),
                 ("crit_cols", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("dense_seps", ctypes.c_int32), ("sparse_seps", ctypes.c_int32),
-                ("device_bytes_plan", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
+                ("device_bytes_plan", ctypes.c_int64), ("coop_items", ctypes.c_int32),
+                ("coop_waves", ctypes.c_int32), ("redo_items", ctypes.c_int32), ("learn_events", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

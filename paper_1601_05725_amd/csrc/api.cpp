@@ -89,6 +89,11 @@ struct basker_ctx {
   DBuf<double> dpanel;
   DBuf<unsigned long long> dbits;
   DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, grpptr;
+  // first-level cooperative schedule
+  DBuf<int32_t> co_item_lo, co_item_hi, co_item_cols, col_item, dep_ptr, dep_idx, sdep_ptr, sdep_idx, item_bad;
+  bool coop = false;
+  int coop_waves = 6;
+  int coop_grid = 0;
   // solve tasks and ND group data of the solve
   DBuf<int32_t> st_kind, st_id, st_need, sg_fd, sg_anc_ptr, sg_anc, sg_choff, s_rowpos, s_status;
   DBuf<int64_t> sg_tbase;
@@ -143,22 +148,29 @@ extern "C" basker_status basker_default_options(basker_options* o) {
   o->fill_order = 1;
   o->nd_leaves = 16;
   o->nd_min_block = 10000;
-  o->capacity_factor = 6.0;
+  o->capacity_factor = 0.0;
   o->device = 0;
   o->stream = nullptr;
   o->refactor_graph = 1;
   o->max_grid = 0;
   o->hbm_budget = 0;
   o->sched_flags = 0;
+  o->item_cols = 0;
+  o->coop_waves = 0;
   return BASKER_OK;
 }
 
 static bool options_valid(const basker_options& o) {
   if (!(o.pivot_tol > 0.0 && o.pivot_tol <= 1.0)) return false;   // also rejects NaN
   if (o.nd_leaves < 1 || (o.nd_leaves & (o.nd_leaves - 1)) != 0) return false;
-  if (o.hbm_budget < 0 || o.max_grid < 0) return false;
+  if (o.hbm_budget < 0 || o.max_grid < 0 || o.item_cols < 0 || o.capacity_factor < 0) return false;
+  if (o.coop_waves != 0 && o.coop_waves != 4 && o.coop_waves != 6 && o.coop_waves != 8) return false;
   return true;
 }
+
+// work budget (visited pattern entries) of the symbolic factorization without row exchanges
+constexpr int64_t kSymVisitBudget = 400000000LL;
+constexpr int kLdsPerCu = 160 * 1024;
 
 extern "C" const char* basker_status_string(basker_status s) {
   switch (s) {
@@ -191,17 +203,93 @@ static int plan_grid(const Plan& P, const basker_options& o) {
 constexpr int kGwsSlots = 1 << 14;   // hash slots of a workgroup's global fallback workspace
 static int64_t gws_stride_bytes() { return ((48LL * kGwsSlots + 16 + 255) / 256) * 256; }
 
-// initial L/U pool entries: capacity_factor * nnz(diagonal blocks) + n
-static int64_t pool_capacity(const Plan& P, const basker_options& o) {
-  const double cf = o.capacity_factor > 0 ? o.capacity_factor : 6.0;
-  int64_t cap = (int64_t)(cf * (double)P.Ri.size()) + P.n + 64;
-  return std::min<int64_t>(cap, 0x7fffffffLL);
-}
 
-// separator columns and their entries bound the first-step buffer initially
+// separator first-step buffer: twice its entries without row exchanges, or a bound
+// from the separator column count
 static int64_t cb_capacity(const Plan& P) {
+  if (P.sym_ok) return std::max<int64_t>(4096, 2 * P.sym_cb);
   const int64_t sepcols = P.lvl_col_ptr.back() - (P.lvl_col_ptr.size() > 1 ? P.lvl_col_ptr[1] : 0);
   return std::max<int64_t>(4096, 256 * sepcols);
+}
+
+// first-level workgroups: one per CU (the waves' LDS workspaces fill a CU's LDS)
+static int coop_grid_of(const Plan& P, const basker_options& o, int waves) {
+  const int per_cu = std::max(1, kLdsPerCu / std::max(1, coop_lds_bytes(waves)));
+  int grid = std::min<int>((int)P.co_item_lo.size(), kNumCu * per_cu);
+  if (o.max_grid > 0) grid = std::min(grid, o.max_grid);
+  return grid;
+}
+
+static int coop_waves_of(const basker_options& o) { return o.coop_waves ? o.coop_waves : 6; }
+
+// Every first-level column in exactly one item with a slot count that matches its
+// segments, and every dependency list ascending inside the column's own segment
+// before the column: what the cooperative kernel's waits and slot arithmetic assume.
+static bool level0_schedule_valid(const Plan& P) {
+  const int n = P.n;
+  if ((int)P.col_item.size() != n || (int)P.dep_ptr.size() != n + 1 || (int)P.sdep_ptr.size() != n + 1) return false;
+  std::vector<int32_t> seen(n, 0);
+  for (size_t it = 0; it < P.co_item_lo.size(); it++) {
+    int64_t cols = 0;
+    for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++) {
+      if (q < P.lvl_ptr[0] || q >= P.lvl_ptr[1]) return false;
+      const int sg = P.lvl_seg[q];
+      for (int k = P.seg_c0[sg]; k < P.seg_c1[sg]; k++) {
+        if (P.col_item[k] != (int32_t)it || seen[k]++) return false;
+        for (int pass = 0; pass < 2; pass++) {
+          const std::vector<int32_t>& ptr = pass ? P.sdep_ptr : P.dep_ptr;
+          const std::vector<int32_t>& idx = pass ? P.sdep_idx : P.dep_idx;
+          int prev = P.seg_c0[sg] - 1;
+          for (int32_t e = ptr[k]; e < ptr[k + 1]; e++) {
+            if (idx[e] <= prev || idx[e] >= k) return false;
+            prev = idx[e];
+          }
+        }
+      }
+      cols += P.seg_c1[sg] - P.seg_c0[sg];
+    }
+    if (cols != P.co_item_cols[it]) return false;
+  }
+  for (int k = 0; k < n; k++)
+    if ((P.col_item[k] >= 0) != (seen[k] == 1)) return false;
+  return true;
+}
+
+static bool coop_usable(const Plan& P) {
+  return !P.co_item_lo.empty() && P.co_max_item_cols <= kCoopMaxItemCols && P.co_valid;
+}
+
+// fallback-workspace regions (one per wavefront of the widest launch)
+static int64_t gws_regions(const Plan& P, const basker_options& o) {
+  int64_t r = plan_grid(P, o);
+  if (coop_usable(P)) {
+    const int w = coop_waves_of(o);
+    r = std::max<int64_t>(r, (int64_t)coop_grid_of(P, o, w) * w);
+  }
+  return r;
+}
+
+// Wavefronts take pool space in chunks of at least kMinChunk entries, and a wave can
+// leave one chunk partly used per launch: the chunk is 1/(kChunkDiv * waves) of the
+// pool, and the pools add kMinChunk per wave and launch of a first level (its
+// speculative and redo passes) and of the separator levels.
+constexpr int64_t kMinChunk = 16;
+constexpr int64_t kChunkDiv = 32;
+
+static int64_t pool_waves(const Plan& P, const basker_options& o) { return gws_regions(P, o); }
+
+// initial L or U pool entries (which = 0: L, 1: U): twice the fill of a factorization
+// without row exchanges (room for row exchanges, chunk slack and first-level items
+// redone after a failed speculation), or capacity_factor * nnz(diagonal blocks)
+static int64_t pool_capacity(const Plan& P, const basker_options& o, int which) {
+  int64_t cap;
+  if (o.capacity_factor > 0 || !P.sym_ok)
+    cap = (int64_t)((o.capacity_factor > 0 ? o.capacity_factor : 6.0) * (double)P.Ri.size());
+  else
+    cap = 2 * (which == 0 ? P.sym_lnz : P.sym_unz);
+  const int64_t launches = 2 + (int64_t)P.lvl_ptr.size();
+  cap += P.n + 64 + kMinChunk * pool_waves(P, o) * launches;
+  return std::min<int64_t>(cap, 0x7fffffffLL);
 }
 
 // Device bytes a handle holds after upload_plan, a factorization without pool growth
@@ -232,9 +320,12 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(8, P.nnz); add(8, nnzd); add(8, nnzo);                       // vals, Rx, OTx
   for (int t = 0; t < 6; t++) add(4, n);                           // pinv, piv, Lbeg..Ucnt
   add(4, kStatusWords); add(8, 3);
-  const int64_t cap = pool_capacity(P, o);
-  add(4, cap); add(8, cap); add(4, cap); add(8, cap);
-  b += gws_stride_bytes() * plan_grid(P, o);
+  const int64_t capL = pool_capacity(P, o, 0), capU = pool_capacity(P, o, 1);
+  add(4, capL); add(8, capL); add(4, capU); add(8, capU);
+  b += gws_stride_bytes() * gws_regions(P, o);
+  const int64_t nco = (int64_t)P.co_item_lo.size();
+  add(4, nco); add(4, nco); add(4, nco); add(4, n); add(4, nco);   // items, col_item, item_bad
+  add(4, n + 1); add(4, (int64_t)P.dep_idx.size()); add(4, n + 1); add(4, (int64_t)P.sdep_idx.size());
   const int64_t nrhs = 8;
   add(8, n * nrhs); add(8, n * nrhs); add(8, n * nrhs);            // W, Z, Bdev
   add(8, P.s_gbuf_total * nrhs);
@@ -343,18 +434,31 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->pool.reserve(3));
   (void)nb;
   // L/U pools
-  const int64_t cap = pool_capacity(P, h->opt);
-  HIPCHK(h, h->Li.reserve(cap));
-  HIPCHK(h, h->Lx.reserve(cap));
-  HIPCHK(h, h->Ui.reserve(cap));
-  HIPCHK(h, h->Ux.reserve(cap));
-  // persistent grid and the global fallback workspace (one region per workgroup)
+  HIPCHK(h, h->Li.reserve(pool_capacity(P, h->opt, 0)));
+  HIPCHK(h, h->Lx.reserve(pool_capacity(P, h->opt, 0)));
+  HIPCHK(h, h->Ui.reserve(pool_capacity(P, h->opt, 1)));
+  HIPCHK(h, h->Ux.reserve(pool_capacity(P, h->opt, 1)));
+  // persistent grid and the global fallback workspace (one region per wavefront)
   const int grid = plan_grid(P, h->opt);
   h->grid = grid;
   h->gws_slots = kGwsSlots;
   h->gws_stride = gws_stride_bytes();
-  HIPCHK(h, h->gws.reserve(h->gws_stride * grid));
-  HIPCHK(h, hipMemsetAsync(h->gws.p, 0xff, (size_t)(h->gws_stride * grid), s));
+  const int64_t regions = gws_regions(P, h->opt);
+  HIPCHK(h, h->gws.reserve(h->gws_stride * regions));
+  HIPCHK(h, hipMemsetAsync(h->gws.p, 0xff, (size_t)(h->gws_stride * regions), s));
+  // first-level cooperative schedule
+  h->coop = coop_usable(P);
+  h->coop_waves = coop_waves_of(h->opt);
+  h->coop_grid = h->coop ? coop_grid_of(P, h->opt, h->coop_waves) : 0;
+  HIPCHK(h, h->co_item_lo.upload(P.co_item_lo, s));
+  HIPCHK(h, h->co_item_hi.upload(P.co_item_hi, s));
+  HIPCHK(h, h->co_item_cols.upload(P.co_item_cols, s));
+  HIPCHK(h, h->col_item.upload(P.col_item, s));
+  HIPCHK(h, h->dep_ptr.upload(P.dep_ptr, s));
+  HIPCHK(h, h->dep_idx.upload(P.dep_idx, s));
+  HIPCHK(h, h->sdep_ptr.upload(P.sdep_ptr, s));
+  HIPCHK(h, h->sdep_idx.upload(P.sdep_idx, s));
+  HIPCHK(h, h->item_bad.reserve((int64_t)P.co_item_lo.size()));
   HIPCHK(h, hipStreamSynchronize(s));
   return BASKER_OK;
 }
@@ -416,6 +520,8 @@ static void fill_info_static(basker_ctx* h) {
       if (P.seg_level[sg] >= 1 && !dense[sg]) I.sparse_seps++;
   }
   I.device_bytes_plan = plan_device_bytes(P, h->opt);
+  I.coop_items = coop_usable(P) ? (int32_t)P.co_item_lo.size() : 0;
+  I.coop_waves = coop_waves_of(h->opt);
 }
 
 extern "C" basker_status basker_symbolic(int32_t n, const int32_t* colptr, const int32_t* rowind, const double* values,
@@ -433,11 +539,11 @@ extern "C" basker_status basker_symbolic(int32_t n, const int32_t* colptr, const
   int rc = build_plan(n, colptr, rowind, values, so, h->plan);
   if (rc != 0) {
     basker_status s = rc == -2 ? BASKER_ERR_STRUCT_SINGULAR : BASKER_ERR_INVALID;
-    std::string m = h->plan.error;
     basker_free(h);
-    (void)m;
     return s;
   }
+  build_level0_schedule(h->plan, h->opt.item_cols ? h->opt.item_cols : 256, kSymVisitBudget);
+  h->plan.co_valid = level0_schedule_valid(h->plan);
   if (h->device >= 0) {
     st = upload_plan(h);
     if (st != BASKER_OK) { basker_free(h); return st; }
@@ -457,6 +563,8 @@ extern "C" basker_status basker_symbolic_ordered(int32_t n, const int32_t* colpt
   if (st != BASKER_OK) return st;
   int rc = build_plan_user(n, colptr, rowind, prow, qcol, nblocks, blkptr, ngroups, grpptr, h->plan);
   if (rc != 0) { basker_free(h); return BASKER_ERR_INVALID; }
+  build_level0_schedule(h->plan, h->opt.item_cols ? h->opt.item_cols : 256, kSymVisitBudget);
+  h->plan.co_valid = level0_schedule_valid(h->plan);
   if (h->device >= 0) {
     st = upload_plan(h);
     if (st != BASKER_OK) { basker_free(h); return st; }
@@ -479,10 +587,12 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.cb_off = h->cb_off.p; a.cb_np = h->cb_np.p; a.cb_nn = h->cb_nn.p;
   a.cbI = h->cbI.p; a.cbX = h->cbX.p; a.cbcap = h->cbI.cap;
   a.mode = 0;
-  // chunk: a fraction of the pool per wave so that idle waves cannot exhaust it
+  // chunk: a fraction of the pool per wave so that the waves' partly used chunks
+  // cannot exhaust it
   {
-    int64_t c = h->Li.cap / (8 * (int64_t)std::max(h->grid, 1));
-    c = std::max<int64_t>(16, std::min<int64_t>(c, 1 << 16));
+    const int64_t waves = std::max<int64_t>(pool_waves(h->plan, h->opt), 1);
+    int64_t c = std::min(h->Li.cap, h->Ui.cap) / (kChunkDiv * waves);
+    c = std::max<int64_t>(kMinChunk, std::min<int64_t>(c, 1 << 16));
     a.chunk = c;
   }
   a.pinv = h->pinv.p; a.piv = h->piv.p;
@@ -496,6 +606,9 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.refactor = refactor;
   a.gws = h->gws.p; a.gws_stride = h->gws_stride; a.gws_slots = h->gws_slots;
   a.reverse = h->opt.sched_flags & 1;
+  a.co_item_lo = h->co_item_lo.p; a.co_item_hi = h->co_item_hi.p; a.co_item_cols = h->co_item_cols.p;
+  a.col_item = h->col_item.p;
+  a.item_bad = h->item_bad.p;
   return a;
 }
 
@@ -540,6 +653,41 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     if (l == 0) {
       a.mode = 0;
       a.level = l;
+      if (h->coop) {
+        // cooperative workgroups over the first level's items: refactorizations wait
+        // for their stored U pattern; factorizations run the predicted lists
+        // speculatively, check them, and redo the failed items with the safe lists
+        const int nco = (int)P.co_item_lo.size();
+        a.item_begin = 0;
+        a.item_end = nco;
+        a.spec = 0;
+        a.redo = 0;
+        if (refactor) {
+          a.dep_src = 1;
+          if ((e = launch_factor_coop(a, h->coop_waves, h->coop_grid, s)) != hipSuccess) return e;
+        } else if (h->opt.sched_flags & 2) {
+          a.dep_src = 0;
+          a.dep_ptr = h->sdep_ptr.p;
+          a.dep_idx = h->sdep_idx.p;
+          if ((e = launch_factor_coop(a, h->coop_waves, h->coop_grid, s)) != hipSuccess) return e;
+        } else {
+          if ((e = launch_fill_i32(h->item_bad.p, 0, nco, s)) != hipSuccess) return e;
+          a.dep_src = 0;
+          a.dep_ptr = h->dep_ptr.p;
+          a.dep_idx = h->dep_idx.p;
+          a.spec = 1;
+          if ((e = launch_factor_coop(a, h->coop_waves, h->coop_grid, s)) != hipSuccess) return e;
+          if ((e = launch_factor_spec_check(a, P.n, nullptr, s)) != hipSuccess) return e;
+          a.spec = 0;
+          a.redo = 1;
+          a.level = nlev;   // the redo pass pops from its own counter
+          a.dep_ptr = h->sdep_ptr.p;
+          a.dep_idx = h->sdep_idx.p;
+          if ((e = launch_factor_coop(a, h->coop_waves, h->coop_grid, s)) != hipSuccess) return e;
+          a.redo = 0;
+        }
+        continue;
+      }
       const int grid = std::min(a.item_end - a.item_begin, h->grid);
       if (grid > 0 && (e = launch_factor_level(a, grid, s)) != hipSuccess) return e;
       continue;
@@ -631,6 +779,34 @@ static bool capture_refactor_graph(basker_ctx* h) {
   h->rgexec = x;
   return true;
 }
+// After first-level items were redone: merge their observed U patterns (the columns
+// each column actually waited for) into the predicted dependency lists, so the next
+// factorization with similar values runs them speculatively again.
+static basker_status learn_deps(basker_ctx* h) {
+  Plan& P = h->plan;
+  const int n = P.n;
+  const int nco = (int)P.co_item_lo.size();
+  hipStream_t s = h->stream;
+  std::vector<int32_t> bad(nco), ub(n), uc(n), ui(h->Uused);
+  HIPCHK(h, hipMemcpyAsync(bad.data(), h->item_bad.p, sizeof(int32_t) * nco, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(ub.data(), h->Ubeg.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(uc.data(), h->Ucnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  if (h->Uused > 0)
+    HIPCHK(h, hipMemcpyAsync(ui.data(), h->Ui.p, sizeof(int32_t) * h->Uused, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  std::vector<int32_t> items;
+  for (int it = 0; it < nco; it++)
+    if (bad[it]) items.push_back(it);
+  merge_learned_deps(P, items, ub, uc, ui);
+  P.co_valid = level0_schedule_valid(P);
+  if (!P.co_valid) h->coop = false;
+  HIPCHK(h, h->dep_ptr.upload(P.dep_ptr, s));
+  HIPCHK(h, h->dep_idx.upload(P.dep_idx, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->info.learn_events++;
+  return BASKER_OK;
+}
+
 static basker_status do_factor(basker_ctx* h) {
   drop_refactor_graph(h);   // pools may move
   for (int attempt = 0; attempt < 8; attempt++) {
@@ -648,8 +824,10 @@ static basker_status do_factor(basker_ctx* h) {
       h->info.unz = h->unz;
       h->info.offdiag_pivots = st[ST_OFFDIAG];
       h->info.dense_seps = st[ST_DSEP];
+      h->info.redo_items = st[ST_REDO];
       h->factored = true;
       h->info.factor_calls++;
+      if (st[ST_REDO] > 0) return learn_deps(h);
       return BASKER_OK;
     }
     h->factored = false;
@@ -663,14 +841,26 @@ static basker_status do_factor(basker_ctx* h) {
       continue;
     }
     if (st[ST_CODE] == DEV_POOL) {
-      // grow to twice the demand seen so far
-      int64_t need = std::max<int64_t>((int64_t)std::max(poolc[0], poolc[1]) * 2, 2 * h->Li.cap);
-      if (need > 0x7fffffffLL) need = 0x7fffffffLL;
-      if (need <= h->Li.cap) return fail(h, BASKER_ERR_OOM, "L/U pool exceeds 2^31 entries");
-      HIPCHK(h, h->Li.reserve(need));
-      HIPCHK(h, h->Lx.reserve(need));
-      HIPCHK(h, h->Ui.reserve(need));
-      HIPCHK(h, h->Ux.reserve(need));
+      // grow the pool(s) that ran out to twice the demand seen so far
+      bool grew = false;
+      const bool l_over = (int64_t)poolc[0] > h->Li.cap, u_over = (int64_t)poolc[1] > h->Ui.cap;
+      if (l_over || !u_over) {
+        int64_t need = std::min<int64_t>(std::max<int64_t>((int64_t)poolc[0] * 2, 2 * h->Li.cap), 0x7fffffffLL);
+        if (need > h->Li.cap) {
+          HIPCHK(h, h->Li.reserve(need));
+          HIPCHK(h, h->Lx.reserve(need));
+          grew = true;
+        }
+      }
+      if (u_over || !l_over) {
+        int64_t need = std::min<int64_t>(std::max<int64_t>((int64_t)poolc[1] * 2, 2 * h->Ui.cap), 0x7fffffffLL);
+        if (need > h->Ui.cap) {
+          HIPCHK(h, h->Ui.reserve(need));
+          HIPCHK(h, h->Ux.reserve(need));
+          grew = true;
+        }
+      }
+      if (!grew) return fail(h, BASKER_ERR_OOM, "L/U pool exceeds 2^31 entries");
       h->info.pool_regrows++;
       continue;
     }

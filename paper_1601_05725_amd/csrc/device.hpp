@@ -32,6 +32,10 @@ enum { ST_CODE = 0, ST_FAILCOL = 1, ST_POOL = 2, ST_WS = 3, ST_OFFDIAG = 4, ST_C
 constexpr int kStatusWords = ST_WORDS;
 enum { DEV_OK = 0, DEV_SINGULAR = 3, DEV_REFACTOR_FAIL = 8, DEV_WORKSPACE = 7, DEV_POOL = 4, DEV_PATTERN = 5,
        DEV_STALL = 9 };
+// status word 7: first-level work items redone after a failed speculation
+constexpr int ST_REDO = 7;
+// the cooperative kernel keeps one done bit per column of an item in LDS
+constexpr int kCoopMaxItemCols = 65536;
 
 struct FactorArgs {
   int32_t n;
@@ -88,6 +92,21 @@ struct FactorArgs {
   int64_t gws_stride;      // bytes per region
   int32_t gws_slots;       // hash slots per region (power of two)
   int32_t reverse;         // hand out work items last first (results do not depend on it)
+  // first level, cooperative kernel: items of consecutive segments (into lvl_seg) with
+  // their column counts, a dependency list per column (dep_src 0: dep_ptr/dep_idx,
+  // ascending column indices inside the segment; 1: the stored U pattern of a
+  // refactorization), speculation (spec) with a per-item failure flag, and the redo
+  // pass (redo: only items whose flag is set, their state cleared first)
+  const int32_t* co_item_lo;
+  const int32_t* co_item_hi;
+  const int32_t* co_item_cols;
+  const int32_t* col_item;
+  const int32_t* dep_ptr;
+  const int32_t* dep_idx;
+  int32_t dep_src;
+  int32_t spec;
+  int32_t redo;
+  int32_t* item_bad;
 };
 
 struct SolveArgs {
@@ -161,6 +180,12 @@ struct DenseSepArgs {
 hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s);
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
+// first level on workgroups of `waves` wavefronts (4, 6 or 8); grid workgroups
+hipError_t launch_factor_coop(const FactorArgs& a, int waves, int grid, hipStream_t s);
+// the speculation check after the first level: a row of L(:,k) pivoted by an earlier
+// column marks k's item for the redo pass
+hipError_t launch_factor_spec_check(const FactorArgs& a, int ncols_level0, const int32_t* cols, hipStream_t s);
+int coop_lds_bytes(int waves);
 hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);

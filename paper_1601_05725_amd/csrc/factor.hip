@@ -103,6 +103,7 @@ struct Ws {
   int H;
   int NP;         // capacity of the pivotal list
   int shift;      // 32 - log2(H)
+  int SC;         // capacity of the stage (entries)
 };
 
 // Per-wave pool allocator: a wave claims a chunk of the L and U pools with one atomic
@@ -117,8 +118,9 @@ struct Alloc {
 constexpr int kStage = 512;   // staged L entries per pass of the update
 
 // H hash slots; the pivotal list holds NP entries (a column overflows to the global
-// workspace once more than H/2 rows are inserted, so NP = H/2 is always enough)
-template <int H, int NP>
+// workspace once more than H/2 rows are inserted, so NP = H/2 is always enough); SC
+// staged L entries
+template <int H, int NP, int SC = kStage>
 struct LdsWs {
   int32_t key[H];
   double val[H];
@@ -129,11 +131,22 @@ struct LdsWs {
   int32_t pb[NP];
   int32_t pc[NP];
   unsigned long long sk[NP];
-  double st_val[kStage];
-  int32_t st_slot[kStage];
+  double st_val[SC];
+  int32_t st_slot[SC];
   int32_t st_pre[72];
   int32_t st_beg[64];
   int32_t cnt[4];
+};
+
+// Speculation context of a column of the first level (cooperative kernel).  A
+// speculative column counts rows pivoted by later columns as not pivotal, and every
+// pivot column its reach uses must be in the dependency list it waited for; a pivot
+// row must not have been claimed already.  Any other outcome is reported (return 3)
+// and the column's work item is redone with safe dependencies.
+struct ColCtx {
+  int spec;
+  const int32_t* deps;   // ascending
+  int ndeps;
 };
 
 __device__ __forceinline__ unsigned hash_of(int32_t r, int shift) {
@@ -328,7 +341,7 @@ struct Pre {
 };
 
 __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al, Pre& pre,
-                                             int knext) {
+                                             int knext, const ColCtx& cx) {
   const int lane = lane_id();
   ws_reset(w);
   const int g0 = a.grp_lo[k], g1 = a.grp_hi[k];
@@ -336,8 +349,9 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
   // separator's descendants, whose columns precede the separator's first column g0.  In
   // a factorization no other row is pivotal yet; a refactorization keeps the previous
   // pivots of every row, so later pivots (the separator's own and its ancestors') must
-  // be read as not pivotal here.
-  const int plim = a.mode == 1 ? g0 : 0x7fffffff;
+  // be read as not pivotal here.  A speculative column likewise ignores the pivots of
+  // later columns that ran before it.
+  const int plim = a.mode == 1 ? g0 : (cx.spec ? k : 0x7fffffff);
   const bool use_pre = a.mode == 0 && !a.refactor && pre.k == k;
   const Pre cur = pre;
   const bool do_pre = a.mode == 0 && !a.refactor && knext >= 0;
@@ -458,6 +472,20 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
     for (int t = lane; t < np; t += 64) w.sk[t] = ((unsigned long long)(unsigned)w.pj[t] << 32) | (unsigned)t;
     wsync();
   }
+  if (cx.spec) {
+    // every pivot column the reach used must be one this column waited for
+    bool miss = false;
+    for (int e = lane; e < np; e += 64) {
+      const int32_t j = (int32_t)(w.sk[e] >> 32);
+      int lo = 0, hi = cx.ndeps;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cx.deps[mid] < j) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= cx.ndeps || cx.deps[lo] != j) miss = true;
+    }
+    if (__any(miss)) return 3;
+  }
 
   // sparse triangular update, ascending pivot order.  The L(:,j) entries of up to 64
   // list entries at a time are gathered into LDS in one wave-wide pass, their rows
@@ -475,7 +503,7 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
     int j0 = 0;
     while (j0 < nb) {
       const int off0 = rl(off, j0);
-      const bool fit = lane >= j0 && lane < nb && off + c - off0 <= kStage;
+      const bool fit = lane >= j0 && lane < nb && off + c - off0 <= w.SC;
       const int nfit = __popcll(__ballot(fit));
       if (nfit == 0) {
         // a column longer than the stage: straight from global memory
@@ -638,6 +666,7 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
 
   if (!a.refactor) {
     if (!(m > 0.0)) {
+      if (cx.spec) return 3;   // decided again with safe dependencies
       if (lane == 0) {
         atomicMax(&a.status[ST_CODE], DEV_SINGULAR);
         atomicMin(&a.status[ST_FAILCOL], k);
@@ -727,7 +756,22 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
       if (s >= 0) a.Lx[lb + t] = w.val[s] / xp;
     }
   }
-  if (lane == 0) a.pinv[p] = k;
+  if (a.refactor) {
+    if (lane == 0) a.pinv[p] = k;
+  } else {
+    // claim the pivot row; a row can be claimed twice only by speculative columns
+    int claimed = 1;
+    if (lane == 0) claimed = atomicCAS(&a.pinv[p], -1, k) == -1;
+    claimed = __shfl(claimed, 0, 64);
+    if (!claimed) {
+      if (cx.spec) return 3;
+      if (lane == 0) {
+        atomicMax(&a.status[ST_CODE], DEV_PATTERN);
+        atomicMin(&a.status[ST_FAILCOL], k);
+      }
+      return 2;
+    }
+  }
   pre.pp = p;
   pre.pk = k;
   return 0;
@@ -746,6 +790,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   wl.H = HS;
   wl.NP = NPS;
   wl.shift = 32 - __builtin_ctz(HS);
+  wl.SC = kStage;
   Ws wg;
   {
     const int H = a.gws_slots;
@@ -764,8 +809,10 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.H = H;
     wg.NP = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
+    wg.SC = kStage;
   }
   wsync();
+  const ColCtx cx0 = {0, nullptr, 0};
   Alloc al = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   Pre pre;
   pre.k = -1;
@@ -781,9 +828,9 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
       if (idx >= ncols) break;
       if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
       const int k = a.col_list[a.col_begin + (a.reverse ? ncols - 1 - idx : idx)];
-      int rc = factor_column(a, wl, k, al, pre, -1);
+      int rc = factor_column(a, wl, k, al, pre, -1, cx0);
       if (rc == 1) {
-        rc = factor_column(a, wg, k, al, pre, -1);
+        rc = factor_column(a, wg, k, al, pre, -1, cx0);
         if (rc == 1 && lane == 0) {
           atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
           atomicMin(&a.status[ST_FAILCOL], k);
@@ -807,9 +854,9 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
         pre.k = -1;
         for (int k = c0; k < c1; k++) {
           const int knext = k + 1 < c1 ? k + 1 : -1;
-          int rc = factor_column(a, wl, k, al, pre, knext);
+          int rc = factor_column(a, wl, k, al, pre, knext, cx0);
           if (rc == 1) {
-            rc = factor_column(a, wg, k, al, pre, knext);
+            rc = factor_column(a, wg, k, al, pre, knext, cx0);
             if (rc == 1 && lane == 0) {
               atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
               atomicMin(&a.status[ST_FAILCOL], k);
@@ -828,6 +875,233 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     if (!a.refactor && (al.lnz || al.unz)) {
       atomicAdd(&a.nnz_ctr[0], (unsigned long long)al.lnz);
       atomicAdd(&a.nnz_ctr[1], (unsigned long long)al.unz);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First level on workgroups of NW wavefronts.  A workgroup takes one work item at a
+// time (a large BTF block or ND leaf, or a run of small blocks); its waves take the
+// item's columns in order from an LDS counter, and a wave starts column k once every
+// column in k's dependency list is done (done bits in LDS, written with a release and
+// read with an acquire at workgroup scope).  Columns are handed out in increasing
+// order and every dependency precedes its column, so the earliest unfinished column
+// can always run: the waits end.  A wait is still bounded (a stall is reported as an
+// error, never a hang).
+//
+// With the dependencies of every pivot sequence (column elimination tree children) or
+// the stored U pattern of a refactorization the result is the serial one.  With
+// predicted dependencies (the U pattern without row exchanges, or one learned from an
+// earlier factorization) the columns run speculatively: ColCtx's checks, the pivot
+// claim and the check kernel after the launch flag every item whose result could
+// differ from the serial one, and the redo pass factors those items again with the
+// elimination-tree lists.  Accepted items are bit for bit the serial result: every
+// row a column touched had the pivot status it has at that point of the serial order,
+// and every L column it used was complete.
+// ---------------------------------------------------------------------------
+constexpr int kCoopStage = 256;
+constexpr int kCoopDoneWords = kCoopMaxItemCols / 32;
+constexpr unsigned kSpinLimit = 1u << 22;
+
+template <int NW>
+struct CoopCfg;
+template <> struct CoopCfg<4> { static constexpr int H = 512; };
+template <> struct CoopCfg<6> { static constexpr int H = 512; };
+template <> struct CoopCfg<8> { static constexpr int H = 256; };
+
+template <int NW>
+struct CoopLds {
+  LdsWs<CoopCfg<NW>::H, CoopCfg<NW>::H / 2, kCoopStage> ws[NW];
+  unsigned done[kCoopDoneWords];
+  int item, slot, bad, skip;
+};
+
+__device__ __forceinline__ bool done_bit(const unsigned* done, int slot) {
+  const unsigned w = __hip_atomic_load(&done[slot >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return (w >> (slot & 31)) & 1u;
+}
+
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
+  constexpr int HS = CoopCfg<NW>::H;
+  BASKER_SHARED(CoopLds<NW>, sm);
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
+  auto& L = sm.ws[wv];
+  for (int t = lane; t < HS; t += 64) L.key[t] = -1;
+  if (lane == 0) { L.cnt[0] = 0; L.cnt[1] = 0; L.cnt[2] = 0; L.cnt[3] = 0; }
+  Ws wl;
+  wl.key = L.key; wl.val = L.val; wl.pv = L.pv; wl.ins = L.ins; wl.pj = L.pj;
+  wl.ps = L.ps; wl.pb = L.pb; wl.pc = L.pc; wl.sk = L.sk; wl.cnt = L.cnt;
+  wl.st_slot = L.st_slot; wl.st_val = L.st_val; wl.st_pre = L.st_pre; wl.st_beg = L.st_beg;
+  wl.H = HS;
+  wl.NP = HS / 2;
+  wl.shift = 32 - __builtin_ctz(HS);
+  wl.SC = kCoopStage;
+  Ws wg;
+  {
+    const int H = a.gws_slots;
+    char* base = a.gws + ((int64_t)blockIdx.x * NW + wv) * a.gws_stride;
+    wg.key = (int32_t*)base;
+    wg.val = (double*)(base + 4ll * H);
+    wg.pv = (int32_t*)(base + 12ll * H);
+    wg.ins = (int32_t*)(base + 16ll * H);
+    wg.pj = (int32_t*)(base + 20ll * H);
+    wg.ps = (int32_t*)(base + 24ll * H);
+    wg.pb = (int32_t*)(base + 28ll * H);
+    wg.pc = (int32_t*)(base + 32ll * H);
+    wg.sk = (unsigned long long*)(base + 40ll * H);
+    wg.cnt = (int32_t*)(base + 48ll * H);
+    wg.st_slot = L.st_slot; wg.st_val = L.st_val; wg.st_pre = L.st_pre; wg.st_beg = L.st_beg;
+    wg.H = H;
+    wg.NP = H;
+    wg.shift = 32 - __builtin_ctz((unsigned)H);
+    wg.SC = kCoopStage;
+  }
+  Alloc al = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  long long sub_l = 0, sub_u = 0;
+  int sub_off = 0;
+  Pre pre;
+  pre.k = -1; pre.pp = -1; pre.pk = -1;
+  const int nitems = a.item_end - a.item_begin;
+  while (true) {
+    __syncthreads();
+    if (tid == 0) {
+      const int idx = atomicAdd(&a.lvl_ctr[a.level], 1);
+      sm.item = idx < nitems ? a.item_begin + (a.reverse ? nitems - 1 - idx : idx) : -1;
+      sm.slot = 0;
+      sm.bad = 0;
+      sm.skip = 0;
+      if (sm.item >= 0 && a.redo) {
+        sm.skip = __hip_atomic_load(&a.item_bad[sm.item], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        if (!sm.skip) atomicAdd(&a.status[ST_REDO], 1);
+      }
+    }
+    __syncthreads();
+    const int it = sm.item;
+    if (it < 0) break;
+    if (sm.skip) continue;
+    const int ncols = a.co_item_cols[it];
+    for (int w = tid; w < ((ncols + 31) >> 5); w += 64 * NW) sm.done[w] = 0u;
+    if (a.redo) {
+      // clear what the failed speculation stored: pivots of the item's rows (the rows of
+      // a diagonal block or ND leaf are its columns' indices), counts and offsets
+      for (int q = a.co_item_lo[it]; q < a.co_item_hi[it]; q++) {
+        const int sg = a.lvl_seg[q];
+        for (int k = a.seg_c0[sg] + tid; k < a.seg_c1[sg]; k += 64 * NW) {
+          a.pinv[k] = -1;
+          if (a.Ucnt[k] > 0) {
+            sub_u += a.Ucnt[k];
+            sub_l += a.Lcnt[k];
+            if (a.piv[k] != k) sub_off++;
+          }
+          a.Lcnt[k] = 0; a.Ucnt[k] = 0; a.Lbeg[k] = 0; a.Ubeg[k] = 0;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    }
+    __syncthreads();
+    // this wave's cursor over the item's segments
+    int q = a.co_item_lo[it], base = 0;
+    while (true) {
+      int slot = 0;
+      if (lane == 0) slot = atomicAdd(&sm.slot, 1);
+      slot = __shfl(slot, 0, 64);
+      if (slot >= ncols) break;
+      while (slot >= base + (a.seg_c1[a.lvl_seg[q]] - a.seg_c0[a.lvl_seg[q]])) {
+        base += a.seg_c1[a.lvl_seg[q]] - a.seg_c0[a.lvl_seg[q]];
+        q++;
+      }
+      const int k = a.seg_c0[a.lvl_seg[q]] + (slot - base);
+      const int32_t* dp;
+      int nd;
+      if (a.dep_src == 1) {
+        dp = a.Ui + a.Ubeg[k];
+        nd = a.Ucnt[k] - 1;
+      } else {
+        dp = a.dep_idx + a.dep_ptr[k];
+        nd = a.dep_ptr[k + 1] - a.dep_ptr[k];
+      }
+      // wait for the dependencies (slots of the same segment: slot - (k - j))
+      bool stalled = false;
+      for (int e = lane; e < nd; e += 64) {
+        const int js = slot - (k - dp[e]);
+        if (js < base || js >= slot) { stalled = true; break; }   // not an earlier column of the segment
+        unsigned spins = 0;
+        while (!done_bit(sm.done, js)) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) { stalled = true; break; }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const bool any_stall = __any(stalled);
+      int rc = 0;
+      if (any_stall) {
+        if (lane == 0) {
+          atomicMax(&a.status[ST_CODE], DEV_STALL);
+          atomicMin(&a.status[ST_FAILCOL], k);
+        }
+        rc = 2;
+      } else if (__hip_atomic_load(&sm.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
+                 ld_relaxed(&a.status[ST_CODE]) != DEV_OK) {
+        rc = 2;   // the item is redone, or the factorization has failed: only release waiters
+      } else {
+        const ColCtx cx = {a.spec, dp, nd};
+        rc = factor_column(a, wl, k, al, pre, -1, cx);
+        if (rc == 1) {
+          rc = factor_column(a, wg, k, al, pre, -1, cx);
+          if (rc == 1) {
+            if (a.spec) {
+              rc = 3;
+            } else if (lane == 0) {
+              atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
+              atomicMin(&a.status[ST_FAILCOL], k);
+              a.status[ST_WS] = 1;
+            }
+          }
+        }
+        if (rc == 3 && lane == 0) {
+          sm.bad = 1;
+          __hip_atomic_store(&a.item_bad[it], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      // publish: the column's L, U, offsets and pivot before its done bit
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) atomicOr(&sm.done[slot >> 5], 1u << (slot & 31));
+    }
+  }
+  // the wave's own columns (lane 0 holds the wave's tallies), and every thread's share
+  // of what a redo took back (each thread cleared its own columns)
+  long long dl = -sub_l, du = -sub_u;
+  int doff = -sub_off;
+  if (lane == 0) {
+    dl += al.lnz;
+    du += al.unz;
+    doff += al.offdiag;
+  }
+  if (doff) atomicAdd(&a.status[ST_OFFDIAG], doff);
+  if (!a.refactor && (dl || du)) {
+    atomicAdd(&a.nnz_ctr[0], (unsigned long long)dl);
+    atomicAdd(&a.nnz_ctr[1], (unsigned long long)du);
+  }
+}
+
+// thread per first-level column (cols, or every column when cols is null): a row of
+// L(:,k) whose pivot column is below k was pivotal when the serial order reaches k, so
+// k's speculation was wrong
+__global__ void factor_spec_check_kernel(FactorArgs a, int ncols, const int32_t* cols) {
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= ncols) return;
+  const int k = cols ? cols[t] : t;
+  const int it = a.col_item[k];
+  if (it < 0 || a.item_bad[it]) return;
+  const int b = a.Lbeg[k], c = a.Lcnt[k];
+  for (int e = 0; e < c; e++) {
+    const int p = a.pinv[a.Li[b + e]];
+    if (p >= 0 && p < k) {
+      a.item_bad[it] = 1;
+      return;
     }
   }
 }
@@ -872,6 +1146,31 @@ hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t 
 
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((factor_kernel<kLdsSlots, kLdsSlots>), dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+int coop_lds_bytes(int waves) {
+  if (waves == 4) return (int)sizeof(CoopLds<4>);
+  if (waves == 6) return (int)sizeof(CoopLds<6>);
+  if (waves == 8) return (int)sizeof(CoopLds<8>);
+  return 0;
+}
+
+hipError_t launch_factor_coop(const FactorArgs& a, int waves, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (waves == 4)
+    hipLaunchKernelGGL(factor_coop_kernel<4>, dim3(grid), dim3(64 * 4), 0, s, a);
+  else if (waves == 8)
+    hipLaunchKernelGGL(factor_coop_kernel<8>, dim3(grid), dim3(64 * 8), 0, s, a);
+  else
+    hipLaunchKernelGGL(factor_coop_kernel<6>, dim3(grid), dim3(64 * 6), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_spec_check(const FactorArgs& a, int ncols, const int32_t* cols, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(factor_spec_check_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, a, ncols,
+                     cols);
   return hipGetLastError();
 }
 

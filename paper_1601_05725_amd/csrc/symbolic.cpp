@@ -2,6 +2,7 @@
 #include "symbolic.hpp"
 
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <numeric>
 
@@ -1297,6 +1298,192 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
   P.seg_grp.assign(P.seg_c0.size(), -1);
   build_levels(P);
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Level-0 cooperative schedule and the fill of a factorization without row exchanges.
+//
+// With the diagonal taken as pivot in every column (the matching puts large entries
+// there, and the threshold rule keeps them unless an entry is over 1/tau times
+// larger), the reach of column k is the closure of struct(R(:,k)) over the L columns
+// of the rows before k (Alg. 1's reach with pivot row i for column i).  Its rows
+// before k are U(:,k) -- the columns k waits for -- and the rest L(:,k).  Row
+// exchanges can change these sets, which the device detects; the column elimination
+// tree gives lists that hold for every pivot sequence (George and Ng).
+// ---------------------------------------------------------------------------
+void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
+  const int n = P.n;
+  const int nlev = (int)P.lvl_ptr.size() - 1;
+  P.co_item_lo.clear(); P.co_item_hi.clear(); P.co_item_cols.clear();
+  P.col_item.assign(n, -1);
+  P.dep_ptr.assign(n + 1, 0); P.dep_idx.clear();
+  P.sdep_ptr.assign(n + 1, 0); P.sdep_idx.clear();
+  P.co_max_item_cols = 0;
+  P.sym_ok = false;
+  P.sym_lnz = P.sym_unz = P.sym_cb = 0;
+  if (nlev < 1 || n == 0) { P.sym_ok = true; return; }
+  // segment of every column, level of every segment
+  std::vector<int32_t> col_seg(n, -1);
+  for (size_t sg = 0; sg < P.seg_c0.size(); sg++)
+    for (int k = P.seg_c0[sg]; k < P.seg_c1[sg]; k++) col_seg[k] = (int32_t)sg;
+  // items over level 0 (lvl_seg is largest first inside a level)
+  {
+    int q0 = P.lvl_ptr[0], q1 = P.lvl_ptr[1];
+    int start = q0, acc = 0;
+    for (int q = q0; q < q1; q++) {
+      const int sz = P.seg_c1[P.lvl_seg[q]] - P.seg_c0[P.lvl_seg[q]];
+      if (acc > 0 && (acc >= co_min_cols || sz >= co_min_cols)) {
+        P.co_item_lo.push_back(start); P.co_item_hi.push_back(q); P.co_item_cols.push_back(acc);
+        start = q;
+        acc = 0;
+      }
+      acc += sz;
+    }
+    if (q1 > start) { P.co_item_lo.push_back(start); P.co_item_hi.push_back(q1); P.co_item_cols.push_back(acc); }
+    for (size_t it = 0; it < P.co_item_lo.size(); it++) {
+      P.co_max_item_cols = std::max(P.co_max_item_cols, P.co_item_cols[it]);
+      for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++)
+        for (int k = P.seg_c0[P.lvl_seg[q]]; k < P.seg_c1[P.lvl_seg[q]]; k++) P.col_item[k] = (int32_t)it;
+    }
+  }
+  // safe lists: children in the column elimination tree, inside the segment
+  {
+    std::vector<int32_t> cnt(n + 1, 0);
+    for (int k = 0; k < n; k++) {
+      const int p = P.parent[k];
+      if (p >= 0 && P.col_item[k] >= 0 && col_seg[p] == col_seg[k]) cnt[p + 1]++;
+    }
+    for (int k = 0; k < n; k++) cnt[k + 1] += cnt[k];
+    P.sdep_ptr = cnt;
+    P.sdep_idx.assign(cnt[n], 0);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int k = 0; k < n; k++) {   // ascending children: k increases
+      const int p = P.parent[k];
+      if (p >= 0 && P.col_item[k] >= 0 && col_seg[p] == col_seg[k]) P.sdep_idx[fill[p]++] = k;
+    }
+  }
+  // symbolic factorization without row exchanges, block by block.  The closure of
+  // struct(R(:,k)) over L columns of rows i < k (pivotal); `pivlim` limits which rows
+  // count as pivotal (the separator first step applies only descendants, rows < g0).
+  std::vector<int32_t> blk_hi(n);
+  for (size_t b = 0; b + 1 < P.blkptr.size(); b++)
+    for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++) blk_hi[k] = P.blkptr[b + 1];
+  std::vector<int64_t> Lb(n, 0), Le(n, 0);   // L(:,k) rows: Lrows[Lb[k] .. Le[k])
+  std::vector<int32_t> Lrows;
+  std::vector<int32_t> mark(n, -1), queue;
+  queue.reserve(1024);
+  int64_t visits = 0;
+  std::vector<int32_t> deps;
+  bool within = true;
+  // reach of column k with rows < pivlim pivotal; fills queue with the reach
+  auto closure = [&](int k, int pivlim, int stamp) {
+    queue.clear();
+    const int b1 = blk_hi[k];
+    for (int32_t p = P.Rp[k]; p < P.Rp[k + 1]; p++) {
+      const int i = P.Ri[p];
+      if (i >= b1) continue;
+      if (mark[i] != stamp) { mark[i] = stamp; queue.push_back(i); }
+    }
+    for (size_t t = 0; t < queue.size(); t++) {
+      const int i = queue[t];
+      if (i >= pivlim) continue;
+      for (int64_t q = Lb[i]; q < Le[i]; q++) {
+        const int r = Lrows[q];
+        if (mark[r] != stamp) { mark[r] = stamp; queue.push_back(r); }
+      }
+      visits += Le[i] - Lb[i];
+    }
+  };
+  // pass 1: level-0 columns (their closures only touch their own segment's columns);
+  // pass 2: separator columns, whose closures use every earlier column
+  std::vector<int32_t> dcnt(n + 1, 0);
+  std::vector<std::vector<int32_t>> dlist(n);
+  int stamp = 0;
+  bool deps_ok = true;
+  for (int pass = 0; pass < 2 && within; pass++) {
+    for (int k = 0; k < n; k++) {
+      const int sg = col_seg[k];
+      const int lvl = sg >= 0 ? P.seg_level[sg] : 0;
+      if ((pass == 0) != (lvl == 0)) continue;
+      if (visits > visit_budget) {
+        within = false;
+        if (pass == 0) deps_ok = false;
+        break;
+      }
+      const int g0 = P.seg_c0[sg];
+      if (lvl >= 1) {
+        // the separator first step: descendants' pivots only (rows before the separator)
+        closure(k, g0, ++stamp);
+        P.sym_cb += (int64_t)queue.size();
+      }
+      closure(k, k, ++stamp);
+      int64_t lc = 0, uc = 1;
+      deps.clear();
+      for (int i : queue) {
+        if (i < k) {
+          uc++;
+          if (lvl == 0 && i >= g0) deps.push_back(i);
+        } else if (i > k) {
+          lc++;
+        }
+      }
+      P.sym_lnz += lc;
+      P.sym_unz += uc;
+      // L(:,k) rows (columns are visited level 0 first, so offsets are kept per column)
+      Lb[k] = (int64_t)Lrows.size();
+      for (int i : queue)
+        if (i > k) Lrows.push_back(i);
+      Le[k] = (int64_t)Lrows.size();
+      if (lvl == 0) {
+        std::sort(deps.begin(), deps.end());
+        dlist[k] = deps;
+      }
+    }
+  }
+  if (deps_ok) {
+    for (int k = 0; k < n; k++) dcnt[k + 1] = dcnt[k] + (int32_t)dlist[k].size();
+    P.dep_ptr = dcnt;
+    P.dep_idx.clear();
+    P.dep_idx.reserve(dcnt[n]);
+    for (int k = 0; k < n; k++) P.dep_idx.insert(P.dep_idx.end(), dlist[k].begin(), dlist[k].end());
+  } else {
+    // the budget ran out: level-0 columns fall back to their safe lists
+    P.dep_ptr = P.sdep_ptr;
+    P.dep_idx = P.sdep_idx;
+  }
+  P.sym_ok = within;
+}
+
+int64_t merge_learned_deps(Plan& P, const std::vector<int32_t>& items, const std::vector<int32_t>& Ubeg,
+                           const std::vector<int32_t>& Ucnt, const std::vector<int32_t>& Ui) {
+  const int n = P.n;
+  std::vector<char> take(n, 0);
+  for (int it : items)
+    for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++)
+      for (int k = P.seg_c0[P.lvl_seg[q]]; k < P.seg_c1[P.lvl_seg[q]]; k++) take[k] = 1;
+  std::vector<int32_t> ptr(n + 1, 0), idx;
+  idx.reserve(P.dep_idx.size());
+  std::vector<int32_t> merged;
+  int64_t added = 0;
+  for (int k = 0; k < n; k++) {
+    const int32_t* a0 = P.dep_idx.data() + P.dep_ptr[k];
+    const int32_t* a1 = P.dep_idx.data() + P.dep_ptr[k + 1];
+    if (take[k] && Ucnt[k] > 0) {
+      // U(:,k) without its diagonal (last), ascending
+      const int32_t* b0 = Ui.data() + Ubeg[k];
+      const int32_t* b1 = b0 + (Ucnt[k] - 1);
+      merged.clear();
+      std::set_union(a0, a1, b0, b1, std::back_inserter(merged));
+      added += (int64_t)merged.size() - (a1 - a0);
+      idx.insert(idx.end(), merged.begin(), merged.end());
+    } else {
+      idx.insert(idx.end(), a0, a1);
+    }
+    ptr[k + 1] = (int32_t)idx.size();
+  }
+  P.dep_ptr = std::move(ptr);
+  P.dep_idx = std::move(idx);
+  return added;
 }
 
 }  // namespace basker

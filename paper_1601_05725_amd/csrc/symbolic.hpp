@@ -78,6 +78,24 @@ struct Plan {
   std::vector<int64_t> sg_tbase;
   std::vector<int32_t> s_rowpos;   // R row of an ND block -> sg_choff[its group] + offset in the group
   int64_t s_gbuf_total = 0;
+  // Level-0 cooperative schedule.  The first level's segments (BTF blocks and ND
+  // leaves) are cut into items for workgroups of several wavefronts (consecutive
+  // segments of lvl_seg's level-0 range, largest first, at least co_min_cols columns
+  // unless a segment is larger); inside an item the waves take columns in order and a
+  // column waits for its dependency list.  Two lists per level-0 column, inside its
+  // segment and ascending: the predicted one, dep_* (the U pattern of a factorization
+  // without row exchanges, or learned from an earlier factorization), and the safe
+  // one, sdep_* (its children in the column elimination tree, which bounds the
+  // dependencies of every pivot sequence).
+  std::vector<int32_t> co_item_lo, co_item_hi, co_item_cols;
+  std::vector<int32_t> col_item;              // level-0 column -> item (-1 elsewhere)
+  std::vector<int32_t> dep_ptr, dep_idx, sdep_ptr, sdep_idx;
+  int32_t co_max_item_cols = 0;
+  bool co_valid = false;                      // set by the library after checking the lists
+  // fill of a factorization without row exchanges, from the host symbolic pass (sizes
+  // the L/U pools and the separator buffer); sym_ok false when the pass was cut short
+  bool sym_ok = false;
+  int64_t sym_lnz = 0, sym_unz = 0, sym_cb = 0;
   int struct_rank = 0;
   double bottleneck = 0.0;
   int max_depth = 0;
@@ -98,6 +116,15 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
                     const int32_t* prow, const int32_t* qcol,
                     int nblk, const int32_t* blkptr, int ngrp, const int32_t* grpptr,
                     Plan& plan);
+
+// Level-0 items and dependency lists, and the fill of a factorization without row
+// exchanges (within a budget of visited pattern entries).
+void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget);
+
+// Merge the dependencies observed in a factorization (U pattern of every level-0 column
+// of the given items) into the predicted lists: returns entries added.
+int64_t merge_learned_deps(Plan& P, const std::vector<int32_t>& items, const std::vector<int32_t>& Ubeg,
+                           const std::vector<int32_t>& Ucnt, const std::vector<int32_t>& Ui);
 
 // exposed for tests of the orderings
 int max_matching(int n, const int32_t* Ap, const int32_t* Ai, const double* Ax, double thresh,

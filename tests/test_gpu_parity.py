@@ -450,3 +450,50 @@ def test_hbm_budget_and_estimate(bk, orc):
     with pytest.raises(bk.BaskerError) as e:
         bk.Handle.symbolic(a, bk.default_options(hbm_budget=est // 2))
     assert e.value.status == bk.ERR_OOM
+
+
+# ---------------------------------------------------------------------------
+# first-level cooperative schedule: speculation, redo, learned dependencies
+# ---------------------------------------------------------------------------
+
+def test_speculation_redo_and_learning(bk, orc):
+    """Natural ordering of an MNA circuit (zero diagonals of the voltage-source rows):
+    the dependencies predicted without row exchanges are wrong, so the speculative
+    first level must detect it, redo the item with elimination-tree dependencies and
+    still give the oracle's factors bit for bit; the observed dependencies are then
+    learned and the next factorization of the same values needs no redo."""
+    a = synth.gen_mna(3000, seed=31)
+    order = orc.Ordering.natural(a.n)
+    h = bk.Handle.symbolic_ordered(a, order.prow, order.qcol, order.blkptr, order.grpptr)
+    assert h.info()["coop_items"] >= 1
+    f = orc.factor(a, order, update_order=orc.ORDER_ASCENDING)
+    assert f.status == 0 and np.count_nonzero(f.piv != np.arange(a.n)) > 0
+    h.factor(a.values)
+    inf = h.info()
+    say("first factor: redo %d learn %d" % (inf["redo_items"], inf["learn_events"]))
+    assert inf["redo_items"] >= 1 and inf["learn_events"] == 1
+    compare_exact(h.extract(), f)
+    h.factor(a.values)
+    inf = h.info()
+    assert inf["redo_items"] == 0 and inf["learn_events"] == 1
+    compare_exact(h.extract(), f)
+    b = synth.rhs(a.n, 1)
+    assert orc.residual(a, h.solve(b), b) <= RES_TOL
+
+
+@pytest.mark.parametrize("waves,flags,item_cols", [(4, 0, 64), (8, 0, 1024), (6, 2, 256), (6, 3, 128)])
+def test_first_level_schedules_agree(bk, orc, waves, flags, item_cols):
+    """Wavefronts per workgroup, item size, reverse item order and the safe-only
+    schedule (flag 2) change who factors which column when; the factors stay the
+    oracle's bit for bit."""
+    inp = synth.gen_batched_btf(nblocks=600, big=6000, seed=19)
+    a = inp.a
+    o = bk.default_options(nd_min_block=3000, nd_leaves=8, coop_waves=waves, sched_flags=flags, item_cols=item_cols)
+    h = bk.Handle.symbolic(a, o)
+    prow, qcol, bp, gp = h.ordering()
+    order = orc.Ordering(prow, qcol, bp, gp)
+    h.factor(a.values)
+    inf = h.info()
+    say("waves %d flags %d items %d redo %d" % (waves, flags, inf["coop_items"], inf["redo_items"]))
+    assert inf["coop_items"] > 1 and inf["coop_waves"] == waves
+    compare_exact(h.extract(), orc.factor(a, order, update_order=orc.ORDER_ASCENDING))
