@@ -257,6 +257,9 @@ def main():
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "factor_kernel_ms": fk_ms,
         "refactor_fallbacks": info["refactor_fallbacks"],
+        "schedule": {"first_level_items": info["coop_items"], "waves_per_workgroup": info["coop_waves"],
+                     "redo_items_last": info["redo_items"], "learn_events": info["learn_events"],
+                     "dense_separators": info["dense_seps"], "pool_regrows": info["pool_regrows"]},
         "solve_kernel_ms": float(np.mean(sk)),
         "scatter_kernel_ms": float(np.mean(sc)),
         "hbm_gbs_factor": achieved,

@@ -91,6 +91,7 @@ struct basker_ctx {
   DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, grpptr;
   // first-level cooperative schedule
   DBuf<int32_t> co_item_lo, co_item_hi, co_item_cols, col_item, dep_ptr, dep_idx, sdep_ptr, sdep_idx, item_bad;
+  DBuf<int32_t> co_item_off, co_issue;
   bool coop = false;
   int coop_waves = 6;
   int coop_grid = 0;
@@ -252,6 +253,27 @@ static bool level0_schedule_valid(const Plan& P) {
   }
   for (int k = 0; k < n; k++)
     if ((P.col_item[k] >= 0) != (seen[k] == 1)) return false;
+  // issue lists: every slot of an item once, with its column and segment start, and every
+  // predicted dependency issued before the column that waits for it
+  if (P.co_item_off.size() != P.co_item_lo.size() + 1) return false;
+  for (size_t it = 0; it < P.co_item_lo.size(); it++) {
+    const int m = P.co_item_cols[it];
+    if (P.co_item_off[it + 1] - P.co_item_off[it] != m) return false;
+    const int32_t* e = P.co_issue.data() + 3 * (size_t)P.co_item_off[it];
+    std::vector<int32_t> pos(m, -1);
+    for (int i = 0; i < m; i++) {
+      const int k = e[3 * i], sl = e[3 * i + 1], c0 = e[3 * i + 2];
+      if (sl < 0 || sl >= m || pos[sl] >= 0 || k < c0 || k >= n || P.col_item[k] != (int32_t)it) return false;
+      pos[sl] = i;
+    }
+    for (int i = 0; i < m; i++) {
+      const int k = e[3 * i], sl = e[3 * i + 1];
+      for (int32_t d = P.dep_ptr[k]; d < P.dep_ptr[k + 1]; d++) {
+        const int js = sl - (k - P.dep_idx[d]);
+        if (js < 0 || pos[js] >= i) return false;
+      }
+    }
+  }
   return true;
 }
 
@@ -326,6 +348,7 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   const int64_t nco = (int64_t)P.co_item_lo.size();
   add(4, nco); add(4, nco); add(4, nco); add(4, n); add(4, nco);   // items, col_item, item_bad
   add(4, n + 1); add(4, (int64_t)P.dep_idx.size()); add(4, n + 1); add(4, (int64_t)P.sdep_idx.size());
+  add(4, (int64_t)P.co_item_off.size()); add(4, (int64_t)P.co_issue.size());
   const int64_t nrhs = 8;
   add(8, n * nrhs); add(8, n * nrhs); add(8, n * nrhs);            // W, Z, Bdev
   add(8, P.s_gbuf_total * nrhs);
@@ -459,6 +482,8 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->sdep_ptr.upload(P.sdep_ptr, s));
   HIPCHK(h, h->sdep_idx.upload(P.sdep_idx, s));
   HIPCHK(h, h->item_bad.reserve((int64_t)P.co_item_lo.size()));
+  HIPCHK(h, h->co_item_off.upload(P.co_item_off, s));
+  HIPCHK(h, h->co_issue.upload(P.co_issue, s));
   HIPCHK(h, hipStreamSynchronize(s));
   return BASKER_OK;
 }
@@ -609,6 +634,9 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.co_item_lo = h->co_item_lo.p; a.co_item_hi = h->co_item_hi.p; a.co_item_cols = h->co_item_cols.p;
   a.col_item = h->col_item.p;
   a.item_bad = h->item_bad.p;
+  a.co_item_off = h->co_item_off.p;
+  a.co_issue = h->co_issue.p;
+  a.use_issue = 0;
   return a;
 }
 
@@ -676,9 +704,11 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
           a.dep_ptr = h->dep_ptr.p;
           a.dep_idx = h->dep_idx.p;
           a.spec = 1;
+          a.use_issue = 1;
           if ((e = launch_factor_coop(a, h->coop_waves, h->coop_grid, s)) != hipSuccess) return e;
           if ((e = launch_factor_spec_check(a, P.n, nullptr, s)) != hipSuccess) return e;
           a.spec = 0;
+          a.use_issue = 0;
           a.redo = 1;
           a.level = nlev;   // the redo pass pops from its own counter
           a.dep_ptr = h->sdep_ptr.p;
@@ -802,6 +832,7 @@ static basker_status learn_deps(basker_ctx* h) {
   if (!P.co_valid) h->coop = false;
   HIPCHK(h, h->dep_ptr.upload(P.dep_ptr, s));
   HIPCHK(h, h->dep_idx.upload(P.dep_idx, s));
+  HIPCHK(h, h->co_issue.upload(P.co_issue, s));
   HIPCHK(h, hipStreamSynchronize(s));
   h->info.learn_events++;
   return BASKER_OK;

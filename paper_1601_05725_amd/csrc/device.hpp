@@ -107,6 +107,9 @@ struct FactorArgs {
   int32_t spec;
   int32_t redo;
   int32_t* item_bad;
+  const int32_t* co_item_off;   // first issue entry of every item
+  const int32_t* co_issue;      // (column, slot, segment start) in the issue order of the speculative pass
+  int32_t use_issue;            // 1: take columns from co_issue; 0: in slot order
 };
 
 struct SolveArgs {

@@ -338,6 +338,7 @@ struct Pre {
   double x;     // the lane's value
   int32_t pv;   // pivot column of the lane's row when loaded
   int pp, pk;   // pivot row and index of the column during which pv was loaded
+  int fresh;    // 1: pv was not loaded (rows and values only); read the pivot status on use
 };
 
 __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, int k, Alloc& al, Pre& pre,
@@ -359,6 +360,7 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
   if (do_pre) {
     pre.b = a.Rp[knext];
     pre.e = a.Rp[knext + 1];
+    pre.fresh = 0;
     if (pre.e - pre.b <= 64) pre.k = knext;
   }
 
@@ -372,7 +374,8 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
         int slot = ws_insert(w, r, &isnew);
         if (slot >= 0) {
           w.val[slot] = cur.x;
-          const int32_t pvr = (r == cur.pp) ? cur.pk : cur.pv;
+          int32_t pvr = cur.fresh ? a.pinv[r] : ((r == cur.pp) ? cur.pk : cur.pv);
+          if (pvr >= plim) pvr = -1;
           w.pv[slot] = pvr;
           if (pvr >= 0) plist_push(w, pvr, slot);
         }
@@ -818,6 +821,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   pre.k = -1;
   pre.pp = -1;
   pre.pk = -1;
+  pre.fresh = 0;
   if (a.mode == 1) {
     // one column at a time: every column of the level's separators is independent here
     const int ncols = a.col_end - a.col_begin;
@@ -963,7 +967,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
   long long sub_l = 0, sub_u = 0;
   int sub_off = 0;
   Pre pre;
-  pre.k = -1; pre.pp = -1; pre.pk = -1;
+  pre.k = -1; pre.pp = -1; pre.pk = -1; pre.fresh = 1;
   const int nitems = a.item_end - a.item_begin;
   while (true) {
     __syncthreads();
@@ -1002,18 +1006,44 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
     __syncthreads();
-    // this wave's cursor over the item's segments
+    // this wave's cursor over the item's segments (slot order)
     int q = a.co_item_lo[it], base = 0;
+    const int32_t* issue = a.use_issue ? a.co_issue + 3ll * a.co_item_off[it] : nullptr;
     while (true) {
-      int slot = 0;
-      if (lane == 0) slot = atomicAdd(&sm.slot, 1);
-      slot = __shfl(slot, 0, 64);
-      if (slot >= ncols) break;
-      while (slot >= base + (a.seg_c1[a.lvl_seg[q]] - a.seg_c0[a.lvl_seg[q]])) {
-        base += a.seg_c1[a.lvl_seg[q]] - a.seg_c0[a.lvl_seg[q]];
-        q++;
+      int i = 0;
+      if (lane == 0) i = atomicAdd(&sm.slot, 1);
+      i = __shfl(i, 0, 64);
+      if (i >= ncols) break;
+      int k, slot, sbase;
+      if (issue) {
+        k = issue[3 * i];
+        slot = issue[3 * i + 1];
+        sbase = slot - (k - issue[3 * i + 2]);
+      } else {
+        slot = i;
+        while (slot >= base + (a.seg_c1[a.lvl_seg[q]] - a.seg_c0[a.lvl_seg[q]])) {
+          base += a.seg_c1[a.lvl_seg[q]] - a.seg_c0[a.lvl_seg[q]];
+          q++;
+        }
+        k = a.seg_c0[a.lvl_seg[q]] + (slot - base);
+        sbase = base;
       }
-      const int k = a.seg_c0[a.lvl_seg[q]] + (slot - base);
+      if (!a.refactor) {
+        // R(:,k)'s rows and values do not depend on other columns: load them while
+        // waiting (its rows' pivot status is read after the wait)
+        const int rb = a.Rp[k], re = a.Rp[k + 1];
+        pre.k = -1;
+        if (re - rb <= 64) {
+          pre.k = k;
+          pre.b = rb;
+          pre.e = re;
+          pre.fresh = 1;
+          if (lane < re - rb) {
+            pre.r = a.Ri[rb + lane];
+            pre.x = a.Rx[rb + lane];
+          }
+        }
+      }
       const int32_t* dp;
       int nd;
       if (a.dep_src == 1) {
@@ -1027,7 +1057,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
       bool stalled = false;
       for (int e = lane; e < nd; e += 64) {
         const int js = slot - (k - dp[e]);
-        if (js < base || js >= slot) { stalled = true; break; }   // not an earlier column of the segment
+        if (js < sbase || js >= slot) { stalled = true; break; }   // not an earlier column of the segment
         unsigned spins = 0;
         while (!done_bit(sm.done, js)) {
           __builtin_amdgcn_s_sleep(1);
@@ -1048,8 +1078,10 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
         rc = 2;   // the item is redone, or the factorization has failed: only release waiters
       } else {
         const ColCtx cx = {a.spec, dp, nd};
+        const Pre pk = pre;
         rc = factor_column(a, wl, k, al, pre, -1, cx);
         if (rc == 1) {
+          pre = pk;
           rc = factor_column(a, wg, k, al, pre, -1, cx);
           if (rc == 1) {
             if (a.spec) {

@@ -1452,6 +1452,42 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
     P.dep_idx = P.sdep_idx;
   }
   P.sym_ok = within;
+  build_issue_order(P);
+}
+
+void build_issue_order(Plan& P) {
+  const int nco = (int)P.co_item_lo.size();
+  P.co_item_off.assign(nco + 1, 0);
+  for (int it = 0; it < nco; it++) P.co_item_off[it + 1] = P.co_item_off[it] + P.co_item_cols[it];
+  P.co_issue.assign(3 * (size_t)P.co_item_off[nco], 0);
+  std::vector<int32_t> col, lvl, ord, seg0;
+  for (int it = 0; it < nco; it++) {
+    const int m = P.co_item_cols[it];
+    col.resize(m);
+    seg0.resize(m);
+    lvl.assign(m, 0);
+    int s = 0;
+    for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++) {
+      const int sg = P.lvl_seg[q];
+      const int c0 = P.seg_c0[sg];
+      for (int k = c0; k < P.seg_c1[sg]; k++, s++) {
+        col[s] = k;
+        seg0[s] = c0;
+        int l = 0;
+        for (int32_t e = P.dep_ptr[k]; e < P.dep_ptr[k + 1]; e++) l = std::max(l, lvl[s - (k - P.dep_idx[e])] + 1);
+        lvl[s] = l;
+      }
+    }
+    ord.resize(m);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return lvl[x] < lvl[y]; });
+    int32_t* out = P.co_issue.data() + 3 * (size_t)P.co_item_off[it];
+    for (int i = 0; i < m; i++) {
+      out[3 * i] = col[ord[i]];
+      out[3 * i + 1] = ord[i];
+      out[3 * i + 2] = seg0[ord[i]];
+    }
+  }
 }
 
 int64_t merge_learned_deps(Plan& P, const std::vector<int32_t>& items, const std::vector<int32_t>& Ubeg,
@@ -1483,6 +1519,7 @@ int64_t merge_learned_deps(Plan& P, const std::vector<int32_t>& items, const std
   }
   P.dep_ptr = std::move(ptr);
   P.dep_idx = std::move(idx);
+  build_issue_order(P);
   return added;
 }
 

@@ -91,6 +91,10 @@ struct Plan {
   std::vector<int32_t> col_item;              // level-0 column -> item (-1 elsewhere)
   std::vector<int32_t> dep_ptr, dep_idx, sdep_ptr, sdep_idx;
   int32_t co_max_item_cols = 0;
+  // issue order of the speculative pass: per item (from co_item_off), (column, slot,
+  // first column of its segment) triples sorted by level in the predicted dependency
+  // graph, so the columns a workgroup's waves take next are independent of each other
+  std::vector<int32_t> co_item_off, co_issue;
   bool co_valid = false;                      // set by the library after checking the lists
   // fill of a factorization without row exchanges, from the host symbolic pass (sizes
   // the L/U pools and the separator buffer); sym_ok false when the pass was cut short
@@ -120,6 +124,9 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
 // Level-0 items and dependency lists, and the fill of a factorization without row
 // exchanges (within a budget of visited pattern entries).
 void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget);
+
+// Issue order of every item from the predicted lists (after they change).
+void build_issue_order(Plan& P);
 
 // Merge the dependencies observed in a factorization (U pattern of every level-0 column
 // of the given items) into the predicted lists: returns entries added.
