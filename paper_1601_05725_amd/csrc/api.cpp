@@ -435,6 +435,7 @@ static basker_status upload_plan(basker_ctx* h) {
     lds_max = std::min(lds_max, 160 * 1024);
     if (lds_max > 65536 && solve_lds_setup((size_t)lds_max) != hipSuccess) lds_max = 65536;
     (void)hipGetLastError();
+    HIPCHK(h, sepdense_setup());
     const size_t fixed = solve_lds_bytes(0);
     h->solve_lds_cap = (int32_t)(((size_t)lds_max - fixed) / sizeof(double));
     const int nsl = (int)P.st_lvl_ptr.size() - 1;

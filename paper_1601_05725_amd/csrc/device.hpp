@@ -180,6 +180,11 @@ struct DenseSepArgs {
   int32_t refactor;
 };
 
+// dense separators: panel rows up to 64 * kMaxPanelWords (one LDS row bitmask), an LDS
+// block of kSepDenseLds bytes (set once per process with sepdense_setup)
+constexpr int kMaxPanelWords = 176;
+constexpr int kSepDenseLds = 128 * 1024;
+hipError_t sepdense_setup();
 hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s);
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);

@@ -6,25 +6,37 @@
 // the rows of its ancestor separators: the only rows these columns can reach.  In
 // circuits with long-range branches this block is close to dense, and the
 // left-looking sweep turns into |s|^2/2 dependent steps.  Here one workgroup factors it
-// right-looking on a dense panel (column-major, rows = s's rows then each ancestor's
-// rows): for k = 0..|s|-1 it picks the pivot of column k, forms L(:,k), and applies the
-// rank-1 update to every later column whose pivot-row entry is structurally nonzero.
+// right-looking on a dense panel (column-major in HBM, rows = s's rows then each
+// ancestor's rows), nb columns at a time:
+//
+//   block     nb columns are loaded into LDS and factored column by column: the pivot
+//             of column k among s's non-pivotal structural rows, L(:,k) = x / x_p on the
+//             column's structure, and the rank-1 update of the block's later columns
+//             whose pivot-row entry is structural;
+//   output    the block's U and L columns are written to the pools, one wave a column;
+//   trailing  every later column c is brought up to date with the block: its entries
+//             in the block's pivot rows follow the block's small triangular recurrence
+//             (entry p_t of column c is u_t once the earlier block columns have updated
+//             it, and it is structural if it was or if fill from an earlier block column
+//             reached it), after which every row of c is updated independently,
+//             a_ic = a_ic - l_it * u_t for t ascending.
 //
 // Same result as the column sweep, bit for bit: each entry receives its updates in
-// ascending pivot order with separately rounded multiply and subtract; structurally
-// zero entries are exactly zero and never win the pivot search (unless the whole
-// candidate set is zero, which is singular either way).  The structure is carried as a
-// bitmask per column (fill merges the pivot column's rows into every column it
-// updates), so the stored L and U patterns are exactly the sparse ones.
+// ascending pivot order with separately rounded multiply and subtract, and an update
+// is applied exactly where the sparse path applies it (row in L(:,k)'s structure,
+// pivot-row entry structural), so structurally zero entries stay exactly zero.  The
+// structure is carried as a bitmask per column (fill merges the L rows of every column
+// that updates it), so the stored L and U patterns are exactly the sparse ones.
 #include "device.hpp"
 
 namespace basker {
 
 namespace {
 
-constexpr int kDT = 1024;          // threads per workgroup
-constexpr int kMaxRowWords = 256;  // panel rows up to 16,384
-constexpr int kMaxPivl = 4096;     // local pivots kept in LDS for separators up to this size
+constexpr int kDT = 1024;             // threads per workgroup
+constexpr int kNW = kDT / 64;
+constexpr int kMaxPivl = 4096;        // local pivots kept in LDS for separators up to this size
+constexpr int kMaxNb = 32;            // block width
 
 __device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
@@ -35,38 +47,59 @@ __device__ __forceinline__ double rl_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ __forceinline__ int local_row(const DenseSepArgs& a, int d, int32_t r) {
-  for (int t = a.rng_ptr[d]; t < a.rng_ptr[d + 1]; t++) {
-    const int32_t g0 = a.rng_g0[t];
-    if (r >= g0 && r < g0 + a.rng_len[t]) return a.rng_loc[t] + (r - g0);
-  }
+// The panel's rows are the row ranges of the separator and its ancestors (one range a
+// group, at most kMaxRanges of them), kept in LDS: r_g0[t] first global row, r_loc[t]
+// first panel row, r_len[t] rows.
+constexpr int kMaxRanges = 32;
+
+struct Ranges {
+  int n;
+  int g0[kMaxRanges];
+  int loc[kMaxRanges];
+  int len[kMaxRanges];
+};
+
+__device__ __forceinline__ int local_row(const Ranges& rg, int32_t r) {
+  for (int t = 0; t < rg.n; t++)
+    if (r >= rg.g0[t] && r < rg.g0[t] + rg.len[t]) return rg.loc[t] + (r - rg.g0[t]);
   return -1;
 }
 
-__device__ __forceinline__ int32_t global_row(const DenseSepArgs& a, int d, int loc) {
-  for (int t = a.rng_ptr[d]; t < a.rng_ptr[d + 1]; t++) {
-    const int l0 = a.rng_loc[t];
-    if (loc >= l0 && loc < l0 + a.rng_len[t]) return a.rng_g0[t] + (loc - l0);
-  }
+__device__ __forceinline__ int32_t global_row(const Ranges& rg, int loc) {
+  for (int t = 0; t < rg.n; t++)
+    if (loc >= rg.loc[t] && loc < rg.loc[t] + rg.len[t]) return rg.g0[t] + (loc - rg.loc[t]);
   return -1;
 }
 
-__global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
-  __shared__ unsigned long long piv_bits[kMaxRowWords];   // rows already pivotal
-  __shared__ unsigned long long lbits[kMaxRowWords];      // rows of L(:,k)
-  __shared__ unsigned long long sk_s[kMaxRowWords];       // structure of column k
+__device__ __forceinline__ bool bit(const unsigned long long* b, int i) { return (b[i >> 6] >> (i & 63)) & 1ull; }
+
+// Rows whose block-column L memberships are kept as one 32-bit mask each (the trailing
+// update then visits only the block columns that update a row).
+constexpr int kRowMaskRows = 4096;
+
+// block width for panel height H: the LDS block holds nb columns of H doubles and two
+// bitmasks of W words each, after the row masks (H words when H <= kRowMaskRows)
+__device__ __forceinline__ int block_width(int H, int W, int m, int lds_bytes) {
+  if (H <= kRowMaskRows) lds_bytes -= 4 * H;
+  int nb = lds_bytes / (8 * H + 16 * W);
+  if (nb > kMaxNb) nb = kMaxNb;
+  if (nb > m) nb = m;
+  return nb < 1 ? 1 : nb;
+}
+
+__global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a, int lds_bytes) {
+  extern __shared__ double blk[];                         // H x nb values, then the bitmasks
+  __shared__ unsigned long long piv_bits[kMaxPanelWords]; // rows already pivotal
   __shared__ int pivl_s[kMaxPivl];                        // local pivot rows (m <= kMaxPivl)
-  __shared__ double red_v[kDT / 64];
-  __shared__ int red_i[kDT / 64];
-  __shared__ int sh_p, sh_fail, sh_hasdiag;
-  __shared__ double sh_xp, sh_xd, sh_m;
-  __shared__ int sh_ub, sh_lb, sh_nu, sh_nl;
-  __shared__ int sh_cnt[kDT / 64];
+  __shared__ double ush[kNW][kMaxNb];                     // per wave: u_t of its trailing column
+  __shared__ double red_v[kNW];
+  __shared__ int red_i[kNW];
+  __shared__ int sh_fail;
+  __shared__ Ranges rg;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int nw = kDT / 64;
   const int d = a.d_begin + blockIdx.x;
   const int sg = a.dsep_seg[d];
   const int c0 = a.seg_c0[sg];
@@ -76,23 +109,54 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
   double* P = a.panel + a.poff[d];
   unsigned long long* S = a.bits + a.soff[d];
   int32_t* pivl = a.piv_local + c0;   // local pivot row of each separator column
+  const bool pl_lds = m <= kMaxPivl;
+  const int nb = block_width(H, W, m, lds_bytes);
+  const bool use_rm = H <= kRowMaskRows;
+  double* Pb = blk;                                                                       // H x nb
+  unsigned long long* Sb = reinterpret_cast<unsigned long long*>(blk + (size_t)H * nb);   // W x nb structure
+  unsigned long long* Lb = Sb + (size_t)W * nb;                                           // W x nb L structure
+  unsigned* rmask = reinterpret_cast<unsigned*>(Lb + (size_t)W * nb);                     // H row masks
 
-  // zero the panel and the structure, clear the pivotal set
+  // zero the panel, clear the pivotal set, ranges into LDS
   for (int64_t i = tid; i < (int64_t)H * m; i += kDT) P[i] = 0.0;
-  for (int64_t i = tid; i < (int64_t)W * m; i += kDT) S[i] = 0ull;
-  for (int i = tid; i < kMaxRowWords; i += kDT) piv_bits[i] = 0ull;
-  if (tid == 0) sh_fail = 0;
+  for (int i = tid; i < kMaxPanelWords; i += kDT) piv_bits[i] = 0ull;
+  if (tid == 0) {
+    sh_fail = 0;
+    const int r0 = a.rng_ptr[d], nr = a.rng_ptr[d + 1] - r0;
+    rg.n = nr;
+    if (nr > kMaxRanges) sh_fail = 1;
+    for (int t = 0; t < nr && t < kMaxRanges; t++) {
+      rg.g0[t] = a.rng_g0[r0 + t];
+      rg.loc[t] = a.rng_loc[r0 + t];
+      rg.len[t] = a.rng_len[r0 + t];
+    }
+  }
   __syncthreads();
-  // the partial columns from the first step: non-pivotal rows with their values
-  for (int k = wv; k < m; k += nw) {
+  if (sh_fail) {
+    if (tid == 0) { atomicMax(&a.status[ST_CODE], DEV_PATTERN); atomicMin(&a.status[ST_FAILCOL], c0); }
+    return;
+  }
+  // the partial columns from the first step: non-pivotal rows with their values; the
+  // structure words of a column are gathered in the wave's part of the (still unused)
+  // block area with LDS atomics, then stored whole
+  for (int k = wv; k < m; k += kNW) {
+    unsigned long long* sw = Sb + (size_t)wv * W;
+    for (int w = lane; w < W; w += 64) sw[w] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     const int c = c0 + k;
     const int off = a.cb_off[c] + a.cb_np[c], nn = a.cb_nn[c];
     for (int t = lane; t < nn; t += 64) {
-      const int loc = local_row(a, d, a.cbI[off + t]);
+      const int loc = local_row(rg, a.cbI[off + t]);
       if (loc < 0) { sh_fail = 1; continue; }
       P[loc + (int64_t)k * H] = a.cbX[off + t];
-      atomicOr(&S[(int64_t)k * W + (loc >> 6)], 1ull << (loc & 63));
+      atomicOr(&sw[loc >> 6], 1ull << (loc & 63));
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int w = lane; w < W; w += 64) S[(int64_t)k * W + w] = sw[w];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   if (sh_fail) {
@@ -102,35 +166,41 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
 
   long long lnz = 0, unz = 0;
   int offdiag = 0;
-  for (int k = 0; k < m; k++) {
-    const int c = c0 + k;
-    const double* Pk = P + (int64_t)k * H;
-    const unsigned long long* Sk = S + (int64_t)k * W;
-    // ---- pivot search over the separator's non-pivotal rows
-    double best = -1.0;
-    int bidx = 0x7fffffff;
-    for (int i = tid; i < m; i += kDT) {
-      if ((piv_bits[i >> 6] >> (i & 63)) & 1ull) continue;
-      const double v = fabs(Pk[i]);
-      if (v > best || (v == best && i < bidx)) { best = v; bidx = i; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bidx, o, 64);
-      if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
-    }
-    if (lane == 0) { red_v[wv] = best; red_i[wv] = bidx; }
+  for (int k0 = 0; k0 < m; k0 += nb) {
+    const int nbk = (m - k0 < nb) ? m - k0 : nb;
+    // ---- load the block (its columns have every update from earlier blocks)
+    for (int64_t i = tid; i < (int64_t)H * nbk; i += kDT) Pb[i] = P[i + (int64_t)k0 * H];
+    for (int i = tid; i < W * nbk; i += kDT) Sb[i] = S[i + (int64_t)k0 * W];
     __syncthreads();
-    if (tid == 0) {
+    // ---- factor the block column by column
+    for (int t = 0; t < nbk; t++) {
+      const int k = k0 + t;
+      const int c = c0 + k;
+      double* Pk = Pb + (size_t)t * H;
+      const unsigned long long* Sk = Sb + (size_t)t * W;
+      // pivot search over the separator's non-pivotal rows (a structurally zero row
+      // holds an exact 0 and attains the maximum only in a singular column)
+      double best = -1.0;
+      int bidx = 0x7fffffff;
+      for (int i = tid; i < m; i += kDT) {
+        if (bit(piv_bits, i)) continue;
+        const double v = fabs(Pk[i]);
+        if (v > best || (v == best && i < bidx)) { best = v; bidx = i; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bidx, o, 64);
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      }
+      if (lane == 0) { red_v[wv] = best; red_i[wv] = bidx; }
+      __syncthreads();
+      // every thread combines the waves' results in the same order: the same decision
       double bm = -1.0;
       int bi = 0x7fffffff;
-      for (int t = 0; t < nw; t++)
-        if (red_v[t] > bm || (red_v[t] == bm && red_i[t] < bi)) { bm = red_v[t]; bi = red_i[t]; }
-      // candidates are the structural, non-pivotal rows of the separator; a structurally
-      // zero row holds an exact 0 in the panel, so it can only attain the maximum when the
-      // column is singular, but the diagonal test must see its structure explicitly
-      const bool dcand = !((piv_bits[k >> 6] >> (k & 63)) & 1ull) && ((Sk[k >> 6] >> (k & 63)) & 1ull);
+      for (int u = 0; u < kNW; u++)
+        if (red_v[u] > bm || (red_v[u] == bm && red_i[u] < bi)) { bm = red_v[u]; bi = red_i[u]; }
+      const bool dcand = !bit(piv_bits, k) && bit(Sk, k);
       int p;
       int fail = 0;
       if (!a.refactor) {
@@ -138,50 +208,69 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
         p = (a.diag_pref && dcand && fabs(Pk[k]) >= a.tau * bm) ? k : bi;
       } else {
         p = a.piv[c] - c0;
-        const bool okp = p >= 0 && p < m && !((piv_bits[p >> 6] >> (p & 63)) & 1ull) &&
-                         ((Sk[p >> 6] >> (p & 63)) & 1ull);
+        const bool okp = p >= 0 && p < m && !bit(piv_bits, p) && bit(Sk, p);
         if (!(okp && (bm > 0.0) && Pk[p] != 0.0 && fabs(Pk[p]) >= a.tau * bm)) fail = DEV_REFACTOR_FAIL;
       }
       if (fail) {
-        sh_fail = fail;
-        atomicMax(&a.status[ST_CODE], fail);
-        atomicMin(&a.status[ST_FAILCOL], c);
-      } else {
-        sh_p = p;
-        sh_xp = Pk[p];
-        pivl[k] = p;
-        if (m <= kMaxPivl) pivl_s[k] = p;
+        if (tid == 0) { atomicMax(&a.status[ST_CODE], fail); atomicMin(&a.status[ST_FAILCOL], c); }
+        return;   // every thread took the same decision
       }
+      const double xp = Pk[p];
+      // L structure: structural, not pivotal, not the pivot
+      unsigned long long* Lk = Lb + (size_t)t * W;
+      for (int w = tid; w < W; w += kDT) {
+        unsigned long long b = Sk[w] & ~piv_bits[w];
+        if ((p >> 6) == w) b &= ~(1ull << (p & 63));
+        Lk[w] = b;
+      }
+      if (tid == 0) {
+        pivl[k] = p;
+        if (pl_lds) pivl_s[k] = p;
+      }
+      __syncthreads();
+      // L(:,k) = x / x_p
+      for (int i = tid; i < H; i += kDT)
+        if (bit(Lk, i)) Pk[i] = Pk[i] / xp;
+      if (tid == 0) piv_bits[p >> 6] |= 1ull << (p & 63);
+      __syncthreads();
+      // rank-1 update of the block's later columns whose pivot-row entry is structural.
+      // Row p is not in L(:,k), so no thread changes the value or the structure bit of
+      // row p that the others test here.
+      for (int t2 = t + 1 + wv; t2 < nbk; t2 += kNW) {
+        unsigned long long* S2 = Sb + (size_t)t2 * W;
+        if (!bit(S2, p)) continue;   // wave-uniform
+        double* Pc = Pb + (size_t)t2 * H;
+        const double u = Pc[p];
+        for (int w = lane; w < W; w += 64) S2[w] |= Lk[w];
+        for (int i = lane; i < H; i += 64)
+          if (bit(Lk, i)) {
+            const double prod = Pk[i] * u;
+            Pc[i] = Pc[i] - prod;
+          }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (sh_fail) return;
-    const int p = sh_p;
-    const double xp = sh_xp;
-    // ---- rows of L(:,k): structural, not pivotal, not the pivot
-    for (int w = tid; w < W; w += kDT) {
-      sk_s[w] = Sk[w];
-      unsigned long long b = Sk[w] & ~piv_bits[w];
-      if ((p >> 6) == w) b &= ~(1ull << (p & 63));
-      lbits[w] = b;
-    }
-    __syncthreads();
-    // ---- outputs of column k (wave 0): counts, pool space, U and L entries
-    if (wv == 0) {
+    // ---- outputs of the block's columns, one wave a column
+    for (int t = wv; t < nbk; t += kNW) {
+      const int k = k0 + t;
+      const int c = c0 + k;
+      const int p = pl_lds ? pivl_s[k] : pivl[k];
+      const double* Pk = Pb + (size_t)t * H;
+      const unsigned long long* Sk = Sb + (size_t)t * W;
+      const unsigned long long* Lk = Lb + (size_t)t * W;
       const int dnp = a.cb_np[c];
       // s-internal U entries: earlier pivots j < k whose row is in the structure of k
       int nu = 0;
       for (int j0 = 0; j0 < k; j0 += 64) {
         const int j = j0 + lane;
         bool in = false;
-        if (j < k) {
-          const int pr = m <= kMaxPivl ? pivl_s[j] : pivl[j];
-          in = (sk_s[pr >> 6] >> (pr & 63)) & 1ull;
-        }
+        if (j < k) in = bit(Sk, pl_lds ? pivl_s[j] : pivl[j]);
         nu += __popcll(__ballot(in));
       }
       int nl = 0;
-      for (int w = 0; w < W; w++) nl += __popcll(lbits[w]);
-      int ub = 0, lb = 0;
+      for (int w = lane; w < W; w += 64) nl += __popcll(Lk[w]);
+      for (int o = 32; o > 0; o >>= 1) nl += __shfl_xor(nl, o, 64);
+      int ub = 0, lb = 0, bad = 0;
       if (lane == 0) {
         if (!a.refactor) {
           ub = (int)atomicAdd(&a.pool_next[1], (unsigned long long)(dnp + nu + 1));
@@ -189,7 +278,7 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
           if ((int64_t)ub + dnp + nu + 1 > a.Ucap || (int64_t)lb + nl > a.Lcap) {
             atomicMax(&a.status[ST_CODE], DEV_POOL);
             a.status[ST_POOL] = 1;
-            sh_fail = DEV_POOL;
+            bad = 1;
           }
         } else {
           ub = a.Ubeg[c];
@@ -197,164 +286,149 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
           if (a.Ucnt[c] != dnp + nu + 1 || a.Lcnt[c] != nl) {
             atomicMax(&a.status[ST_CODE], DEV_PATTERN);
             atomicMin(&a.status[ST_FAILCOL], c);
-            sh_fail = DEV_PATTERN;
+            bad = 1;
           }
         }
-        sh_ub = ub;
-        sh_lb = lb;
       }
       ub = __shfl(ub, 0, 64);
       lb = __shfl(lb, 0, 64);
-      if (!__any(lane == 0 && sh_fail != 0)) {
-        // U: descendant part from the first step, then s-internal ascending, then diagonal
-        const int off = a.cb_off[c];
-        for (int t = lane; t < dnp; t += 64) {
-          a.Ui[ub + t] = a.cbI[off + t];
-          a.Ux[ub + t] = a.cbX[off + t];
+      if (__shfl(bad, 0, 64)) continue;
+      // U: descendant part from the first step, then s-internal ascending, then diagonal
+      const int off = a.cb_off[c];
+      for (int u = lane; u < dnp; u += 64) {
+        if (!a.refactor) a.Ui[ub + u] = a.cbI[off + u];
+        a.Ux[ub + u] = a.cbX[off + u];
+      }
+      int pos = dnp;
+      for (int j0 = 0; j0 < k; j0 += 64) {
+        const int j = j0 + lane;
+        bool in = false;
+        int pr = 0;
+        if (j < k) {
+          pr = pl_lds ? pivl_s[j] : pivl[j];
+          in = bit(Sk, pr);
         }
-        int pos = dnp;
-        for (int j0 = 0; j0 < k; j0 += 64) {
-          const int j = j0 + lane;
-          bool in = false;
-          int pr = 0;
-          if (j < k) {
-            pr = m <= kMaxPivl ? pivl_s[j] : pivl[j];
-            in = (sk_s[pr >> 6] >> (pr & 63)) & 1ull;
-          }
-          const unsigned long long bm = __ballot(in);
-          if (in) {
-            const int q = pos + __popcll(bm & ((1ull << lane) - 1ull));
-            a.Ui[ub + q] = c0 + j;
-            a.Ux[ub + q] = Pk[pr];
-          }
-          pos += __popcll(bm);
+        const unsigned long long bm = __ballot(in);
+        if (in) {
+          const int q = pos + __popcll(bm & ((1ull << lane) - 1ull));
+          if (!a.refactor) a.Ui[ub + q] = c0 + j;
+          a.Ux[ub + q] = Pk[pr];
         }
-        if (lane == 0) {
+        pos += __popcll(bm);
+      }
+      if (lane == 0) {
+        a.Ux[ub + pos] = Pk[p];
+        if (!a.refactor) {
           a.Ui[ub + pos] = c;
-          a.Ux[ub + pos] = xp;
           a.Ubeg[c] = ub;
           a.Ucnt[c] = dnp + nu + 1;
           a.Lbeg[c] = lb;
           a.Lcnt[c] = nl;
           a.piv[c] = c0 + p;
-          a.pinv[c0 + p] = c;
+        }
+        a.pinv[c0 + p] = c;
+      }
+      if (!a.refactor) {
+        // L: structure rows in ascending local order, 64 rows (one word) at a time
+        int q = 0;
+        for (int w = 0; w < W; w++) {
+          const unsigned long long b = Lk[w];
+          if (!b) continue;
+          if ((b >> lane) & 1ull) {
+            const int r = (w << 6) + lane;
+            const int qq = q + __popcll(b & ((1ull << lane) - 1ull));
+            a.Li[lb + qq] = global_row(rg, r);
+            a.Lx[lb + qq] = Pk[r];
+          }
+          q += __popcll(b);
         }
         unz += dnp + nu + 1;
         lnz += nl;
-        if (p != k) offdiag++;
+      } else {
+        // stored row order: look every stored row up in the block
+        for (int u = lane; u < nl; u += 64) {
+          const int loc = local_row(rg, a.Li[lb + u]);
+          if (loc >= 0) a.Lx[lb + u] = Pk[loc];
+        }
       }
+      if (p != k) offdiag++;
     }
-    __syncthreads();
-    if (sh_fail) return;
-    // ---- L values (kept in the panel column for the update) and their storage
-    {
-      const int lb = sh_lb;
-      // ascending local row order: prefix over words
-      int base = 0;
-      for (int w0 = 0; w0 < W; w0 += kDT) {
-        const int w = w0 + tid;
-        int cnt = (w < W) ? __popcll(lbits[w]) : 0;
-        // block-wide exclusive scan of cnt over w (two levels: wave, then waves)
-        int incl = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int t = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += t;
+    // ---- bring every later column up to date with the block, one wave a column
+    if (k0 + nbk < m) {
+      if (use_rm) {
+        // row i's mask: bit t set when row i is in L(:, k0 + t)
+        for (int i = tid; i < H; i += kDT) {
+          unsigned mk = 0u;
+          for (int t = 0; t < nbk; t++) mk |= (unsigned)bit(Lb + (size_t)t * W, i) << t;
+          rmask[i] = mk;
         }
-        if (lane == 63) sh_cnt[wv] = incl;
         __syncthreads();
-        int wpre = 0;
-        for (int t = 0; t < wv; t++) wpre += sh_cnt[t];
-        int tot = 0;
-        for (int t = 0; t < nw; t++) tot += sh_cnt[t];
-        __syncthreads();
-        if (w < W) {
-          int q = base + wpre + incl - cnt;
-          unsigned long long b = lbits[w];
-          while (b) {
-            const int bit = __builtin_ctzll(b);
-            b &= b - 1;
-            const int r = (w << 6) + bit;
-            const double l = Pk[r] / xp;
-            P[r + (int64_t)k * H] = l;
-            if (!a.refactor) {
-              a.Li[lb + q] = global_row(a, d, r);
-              a.Lx[lb + q] = l;
-            }
-            q++;
+      }
+      const int p_l = lane < nbk ? (pl_lds ? pivl_s[k0 + lane] : pivl[k0 + lane]) : 0;
+      for (int cc = k0 + nbk + wv; cc < m; cc += kNW) {
+        double* Pc = P + (int64_t)cc * H;
+        unsigned long long* Scol = S + (int64_t)cc * W;
+        // lane t < nbk: the column's entry in pivot row p_t and whether it is structural
+        double ut = 0.0;
+        bool st = false;
+        if (lane < nbk) {
+          ut = Pc[p_l];
+          st = bit(Scol, p_l);
+        }
+        // the block's recurrence, t ascending: a structural u_t updates (and fills) the
+        // pivot rows of the later block columns that are in L(:, k0 + t)
+        for (int t = 0; t < nbk; t++) {
+          if (!rl((int)st, t)) continue;
+          const double u = rl_d(ut, t);
+          if (lane > t && lane < nbk && bit(Lb + (size_t)t * W, p_l)) {
+            const double prod = Pb[(size_t)t * H + p_l] * u;
+            ut = ut - prod;
+            st = true;
           }
         }
-        base += tot;
-      }
-      if (a.refactor) {
-        // stored row order: look every stored row up in the panel
-        __syncthreads();
-        const int cnt = a.Lcnt[c];
-        for (int t = tid; t < cnt; t += kDT) {
-          const int loc = local_row(a, d, a.Li[lb + t]);
-          if (loc >= 0) a.Lx[lb + t] = P[loc + (int64_t)k * H];
-        }
-      }
-    }
-    if (tid == 0) piv_bits[p >> 6] |= 1ull << (p & 63);
-    __syncthreads();
-    // ---- rank-1 update of every later column whose pivot-row entry is structural
-    // (columns k and cc are distinct, so their panel columns do not overlap: the loads of
-    // four words are issued together before the stores)
-    const double* __restrict__ Lk = P + (int64_t)k * H;
-    // this wave's later columns cc = k + 1 + wv + nw * t, 64 at a time: one lane per
-    // column tests the pivot row's structure bit and loads the multiplier, then the
-    // columns with the bit set are updated one after another by the whole wave
-    for (int t0 = 0; k + 1 + wv + nw * t0 < m; t0 += 64) {
-      const int ccl = k + 1 + wv + nw * (t0 + lane);
-      bool on = false;
-      double ul = 0.0;
-      if (ccl < m) {
-        on = (S[(int64_t)ccl * W + (p >> 6)] >> (p & 63)) & 1ull;
-        if (on) ul = P[(int64_t)ccl * H + p];
-      }
-      unsigned long long act = __ballot(on);
-      while (act) {
-        const int j = __ffsll((long long)act) - 1;
-        act &= act - 1;
-        const int cc = rl(ccl, j);
-        const double u = rl_d(ul, j);
-        unsigned long long* __restrict__ Sc = S + (int64_t)cc * W;
-        double* __restrict__ Pc = P + (int64_t)cc * H;
-        for (int w = lane; w < W; w += 64) {
-          const unsigned long long b = lbits[w];
-          if (b) Sc[w] |= b;
-        }
-        for (int w0 = 0; w0 < W; w0 += 4) {
-          double lv[4], cv[4];
-          bool onw[4];
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            const int w = w0 + t;
-            onw[t] = w < W && ((lbits[w] >> lane) & 1ull);
-            lv[t] = 0.0;
-            cv[t] = 0.0;
-            if (onw[t]) {
-              lv[t] = Lk[(w << 6) + lane];
-              cv[t] = Pc[(w << 6) + lane];
+        const unsigned long long smask = __ballot(st) & ((nbk >= 64) ? ~0ull : ((1ull << nbk) - 1ull));
+        if (lane < nbk) ush[wv][lane] = ut;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // every row: a_ic = a_ic - l_it * u_t for every structural u_t, t ascending
+        if (smask) {
+          for (int i = lane; i < H; i += 64) {
+            unsigned eff;
+            if (use_rm) {
+              eff = rmask[i] & (unsigned)smask;
+            } else {
+              eff = 0u;
+              for (int t = 0; t < nbk; t++)
+                if (((smask >> t) & 1ull) && bit(Lb + (size_t)t * W, i)) eff |= 1u << t;
             }
-          }
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            if (onw[t]) {
-              const double prod = lv[t] * u;
-              Pc[((w0 + t) << 6) + lane] = cv[t] - prod;
+            if (!eff) continue;
+            double x = Pc[i];
+            while (eff) {
+              const int t = __builtin_ctz(eff);
+              eff &= eff - 1u;
+              const double prod = Pb[(size_t)t * H + i] * ush[wv][t];
+              x = x - prod;
             }
+            Pc[i] = x;
           }
         }
+        // structure: the L rows of every block column with a structural u_t
+        if (smask) for (int w = lane; w < W; w += 64) {
+          unsigned long long b = Scol[w];
+          for (int t = 0; t < nbk; t++)
+            if ((smask >> t) & 1ull) b |= Lb[(size_t)t * W + w];
+          Scol[w] = b;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
   }
-  if (wv == 0 && lane == 0) {
-    atomicAdd(&a.status[ST_DSEP], 1);
+  if (tid == 0) atomicAdd(&a.status[ST_DSEP], 1);
+  if (lane == 0) {
     if (offdiag) atomicAdd(&a.status[ST_OFFDIAG], offdiag);
-    if (!a.refactor) {
+    if (!a.refactor && (lnz || unz)) {
       atomicAdd(&a.nnz_ctr[0], (unsigned long long)lnz);
       atomicAdd(&a.nnz_ctr[1], (unsigned long long)unz);
     }
@@ -363,9 +437,14 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a) {
 
 }  // namespace
 
+hipError_t sepdense_setup() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&sepdense_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kSepDenseLds);
+}
+
 hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s) {
   if (nsep <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sepdense_kernel, dim3(nsep), dim3(kDT), 0, s, a);
+  hipLaunchKernelGGL(sepdense_kernel, dim3(nsep), dim3(kDT), kSepDenseLds, s, a, kSepDenseLds);
   return hipGetLastError();
 }
 

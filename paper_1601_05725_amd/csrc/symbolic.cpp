@@ -973,7 +973,7 @@ void build_levels(Plan& P) {
       continue;
     int64_t H = 0;
     for (int g = P.seg_grp[s]; g >= 0; g = P.grp_parent[g]) H += P.grpptr[g + 1] - P.grpptr[g];
-    if (H <= 16384) dense[s] = 1;   // panel rows fit the kernel's row bitmaps
+    if (H <= 11264) dense[s] = 1;   // panel rows fit the dense kernel's row bitmaps (176 words)
   }
   P.lvl_ptr.assign(nl + 1, 0);
   for (int s = 0; s < ns; s++) P.lvl_ptr[P.seg_level[s] + 1]++;
