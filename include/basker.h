@@ -119,7 +119,9 @@ typedef struct {
   int32_t coop_waves;        /* wavefronts per first-level workgroup */
   int32_t redo_items;        /* first-level items the last factorization redid after a failed speculation */
   int32_t learn_events;      /* factorizations whose observed dependencies were merged into the schedule */
-  int32_t reserved[4];
+  int32_t reserved0;
+  double rows_kernel_ms;     /* device time of the row-wise copies of L and U built after the last
+                                successful factor/refactor (used by the solve) */
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */
@@ -167,8 +169,7 @@ basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb
  * (column-major, leading dimension ldb >= n) that calls no allocating routine.  Its
  * work vectors live in a static device array of 4,194,304 doubles (32 MiB), which
  * every GPU the library runs on holds until the process ends; a solve needing more
- * than (2 n + the ND node buffers) * nrhs of them fails with BASKER_ERR_WORKSPACE
- * before any device work.  Calls on one GPU share that array, so calls that overlap
+ * than 2 n nrhs of them fails with BASKER_ERR_WORKSPACE before any device work.  Calls on one GPU share that array, so calls that overlap
  * on one GPU (different handles, streams or threads) race and must be serialised by
  * the caller.  Same kernels and results as basker_solve. */
 basker_status basker_solve_noalloc(basker_handle h, int32_t nrhs, double* B, int32_t ldb);

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbasker_mi355x.so")
-SOURCES = ["api.cpp", "symbolic.cpp", "factor.hip", "sepdense.hip", "solve.hip"]
+SOURCES = ["api.cpp", "symbolic.cpp", "factor.hip", "sepdense.hip", "solve.hip", "rows.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -95,10 +95,11 @@ struct basker_ctx {
   bool coop = false;
   int coop_waves = 6;
   int coop_grid = 0;
-  // solve tasks and ND group data of the solve
-  DBuf<int32_t> st_kind, st_id, st_need, sg_fd, sg_anc_ptr, sg_anc, sg_choff, s_rowpos, s_status;
-  DBuf<int64_t> sg_tbase;
-  DBuf<double> gbuf;
+  // solve tasks, row-wise factors (rebuilt after every factorization), done flags
+  DBuf<int32_t> st_kind, st_id, s_status, sflag, LTp, UTp;
+  DBuf<unsigned long long> lkeys, lkeys_out, ukeys, ukeys_out;
+  DBuf<double> lvals, lvals_out, uvals, uvals_out, diag;
+  DBuf<char> rows_temp;
   std::vector<int32_t> st_lvl_lds;   // LDS work doubles of every solve level
   int32_t solve_lds_cap = 0;
   // numeric state
@@ -314,6 +315,15 @@ static int64_t pool_capacity(const Plan& P, const basker_options& o, int which) 
   return std::min<int64_t>(cap, 0x7fffffffLL);
 }
 
+// bytes of the radix sort's workspace for up to `items` pairs: the sort's own answer,
+// or a bound when it cannot be asked
+static int64_t rows_temp_estimate(int64_t items, int n) {
+  size_t b = 0;
+  if (rows_temp_bytes(std::max<int64_t>(items, 1), n, &b) == hipSuccess) return std::max<int64_t>((int64_t)b, 1);
+  (void)hipGetLastError();
+  return 16 * items + (8 << 20);
+}
+
 // Device bytes a handle holds after upload_plan, a factorization without pool growth
 // and a solve of 8 host right-hand sides: the same reservations, added up.
 static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
@@ -337,8 +347,8 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(8, 2); add(4, 2 * nlev);
   add(4, n + 1); add(4, nnzo); add(4, nnzo);                       // OTp, OTj, OTmap
   add(4, n); add(4, n); add(4, nb + 1); add(4, ng + 1);            // prow, qcol, blkptr, grpptr
-  add(4, nt); add(4, nt); add(4, nt);
-  add(4, ng); add(4, ng + 1); add(4, (int64_t)P.sg_anc.size()); add(4, ng); add(8, ng); add(4, n); add(4, 1);
+  add(4, nt); add(4, nt); add(4, 1); add(4, n); add(4, n + 1); add(4, n + 1);   // tasks, status, flags, row pointers
+  add(8, n);                                                                     // U's diagonal
   add(8, P.nnz); add(8, nnzd); add(8, nnzo);                       // vals, Rx, OTx
   for (int t = 0; t < 6; t++) add(4, n);                           // pinv, piv, Lbeg..Ucnt
   add(4, kStatusWords); add(8, 3);
@@ -351,7 +361,12 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(4, (int64_t)P.co_item_off.size()); add(4, (int64_t)P.co_issue.size());
   const int64_t nrhs = 8;
   add(8, n * nrhs); add(8, n * nrhs); add(8, n * nrhs);            // W, Z, Bdev
-  add(8, P.s_gbuf_total * nrhs);
+  // row-wise factors: keys and values, sorted copies, sort workspace, over the fill
+  // without row exchanges (the pools' used extents), or the pools when not counted
+  const int64_t rl = P.sym_ok ? P.sym_lnz + P.sym_lnz / 4 + 4096 : capL;
+  const int64_t ru = P.sym_ok ? P.sym_unz + P.sym_unz / 4 + 4096 : capU;
+  add(32, rl); add(32, ru);
+  b += rows_temp_estimate(std::max(rl, ru), (int)n);
   return b;
 }
 
@@ -365,19 +380,21 @@ static basker_status upload_plan(basker_ctx* h) {
   std::vector<int32_t> glo(n), ghi(n);
   for (size_t g = 0; g + 1 < P.grpptr.size(); g++)
     for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) { glo[k] = P.grpptr[g]; ghi[k] = P.grpptr[g + 1]; }
-  // off-diagonal part by row (CSR), columns ascending inside each row
+  // off-diagonal part by row (CSR), in the order the block back-substitution subtracts
+  // it from a row: later blocks first, columns ascending inside a block
   std::vector<int32_t> OTp(n + 1, 0), OTj(P.Oi.size()), OTmap(P.Oi.size());
   for (size_t q = 0; q < P.Oi.size(); q++) OTp[P.Oi[q] + 1]++;
   for (int i = 0; i < n; i++) OTp[i + 1] += OTp[i];
   {
     std::vector<int32_t> fillp(OTp.begin(), OTp.end() - 1);
-    for (int k = 0; k < n; k++)
-      for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) {
-        int32_t i = P.Oi[q];
-        OTj[fillp[i]] = k;
-        OTmap[fillp[i]] = P.Omap[q];
-        fillp[i]++;
-      }
+    for (int b = (int)P.blkptr.size() - 2; b >= 0; b--)
+      for (int k = P.blkptr[b]; k < P.blkptr[b + 1]; k++)
+        for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) {
+          int32_t i = P.Oi[q];
+          OTj[fillp[i]] = k;
+          OTmap[fillp[i]] = P.Omap[q];
+          fillp[i]++;
+        }
   }
   const int nb = (int)P.blkptr.size() - 1;
   const int nlev = (int)P.lvl_ptr.size() - 1;
@@ -419,14 +436,11 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->grpptr.upload(P.grpptr, s));
   HIPCHK(h, h->st_kind.upload(P.st_kind, s));
   HIPCHK(h, h->st_id.upload(P.st_id, s));
-  HIPCHK(h, h->st_need.upload(P.st_need, s));
-  HIPCHK(h, h->sg_fd.upload(P.sg_fd, s));
-  HIPCHK(h, h->sg_anc_ptr.upload(P.sg_anc_ptr, s));
-  HIPCHK(h, h->sg_anc.upload(P.sg_anc, s));
-  HIPCHK(h, h->sg_choff.upload(P.sg_choff, s));
-  HIPCHK(h, h->sg_tbase.upload(P.sg_tbase, s));
-  HIPCHK(h, h->s_rowpos.upload(P.s_rowpos, s));
   HIPCHK(h, h->s_status.reserve(1));
+  HIPCHK(h, h->sflag.reserve(n));
+  HIPCHK(h, h->LTp.reserve(n + 1));
+  HIPCHK(h, h->UTp.reserve(n + 1));
+  HIPCHK(h, h->diag.reserve(n));
   {
     // LDS per solve launch: the largest work area of the level that fits the device
     int lds_max = 0;
@@ -436,8 +450,9 @@ static basker_status upload_plan(basker_ctx* h) {
     if (lds_max > 65536 && solve_lds_setup((size_t)lds_max) != hipSuccess) lds_max = 65536;
     (void)hipGetLastError();
     HIPCHK(h, sepdense_setup());
-    const size_t fixed = solve_lds_bytes(0);
-    h->solve_lds_cap = (int32_t)(((size_t)lds_max - fixed) / sizeof(double));
+    int32_t cap = (int32_t)((size_t)lds_max / sizeof(double));
+    while (cap > 0 && solve_lds_bytes(cap) > (size_t)lds_max) cap--;
+    h->solve_lds_cap = cap;
     const int nsl = (int)P.st_lvl_ptr.size() - 1;
     h->st_lvl_lds.assign(std::max(nsl, 0), 0);
     for (int l = 0; l < nsl; l++)
@@ -810,6 +825,39 @@ static bool capture_refactor_graph(basker_ctx* h) {
   h->rgexec = x;
   return true;
 }
+// Row-wise copies of the factors for the solve (rows.hip), after every successful
+// factorization or refactorization: buffers sized by the pools' used extents.
+static basker_status build_rows(basker_ctx* h) {
+  hipStream_t s = h->stream;
+  const int64_t lu = std::max<int64_t>(h->Lused, 1), uu = std::max<int64_t>(h->Uused, 1);
+  HIPCHK(h, h->lkeys.reserve(lu)); HIPCHK(h, h->lkeys_out.reserve(lu));
+  HIPCHK(h, h->lvals.reserve(lu)); HIPCHK(h, h->lvals_out.reserve(lu));
+  HIPCHK(h, h->ukeys.reserve(uu)); HIPCHK(h, h->ukeys_out.reserve(uu));
+  HIPCHK(h, h->uvals.reserve(uu)); HIPCHK(h, h->uvals_out.reserve(uu));
+  size_t tb = 0;
+  HIPCHK(h, rows_temp_bytes(std::max(lu, uu), h->plan.n, &tb));
+  HIPCHK(h, h->rows_temp.reserve(std::max<int64_t>((int64_t)tb, 1)));
+  RowsArgs r{};
+  r.n = h->plan.n;
+  r.pinv = h->pinv.p;
+  r.Lbeg = h->Lbeg.p; r.Lcnt = h->Lcnt.p; r.Li = h->Li.p; r.Lx = h->Lx.p;
+  r.Ubeg = h->Ubeg.p; r.Ucnt = h->Ucnt.p; r.Ui = h->Ui.p; r.Ux = h->Ux.p;
+  r.Lused = h->Lused; r.Uused = h->Uused;
+  r.lkeys = h->lkeys.p; r.lvals = h->lvals.p; r.lkeys_out = h->lkeys_out.p; r.lvals_out = h->lvals_out.p;
+  r.ukeys = h->ukeys.p; r.uvals = h->uvals.p; r.ukeys_out = h->ukeys_out.p; r.uvals_out = h->uvals_out.p;
+  r.temp = h->rows_temp.p;
+  r.temp_bytes = (size_t)h->rows_temp.cap;
+  r.LTp = h->LTp.p; r.UTp = h->UTp.p;
+  r.diag = h->diag.p;
+  HIPCHK(h, hipEventRecord(h->ev[4], s));
+  HIPCHK(h, launch_rows_build(r, s));
+  HIPCHK(h, hipEventRecord(h->ev[5], s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev[4], h->ev[5]) == hipSuccess) h->info.rows_kernel_ms = ms;
+  return BASKER_OK;
+}
+
 // After first-level items were redone: merge their observed U patterns (the columns
 // each column actually waited for) into the predicted dependency lists, so the next
 // factorization with similar values runs them speculatively again.
@@ -859,8 +907,13 @@ static basker_status do_factor(basker_ctx* h) {
       h->info.redo_items = st[ST_REDO];
       h->factored = true;
       h->info.factor_calls++;
-      if (st[ST_REDO] > 0) return learn_deps(h);
-      return BASKER_OK;
+      if (st[ST_REDO] > 0) {
+        basker_status lr = learn_deps(h);
+        if (lr != BASKER_OK) return lr;
+      }
+      basker_status rr = build_rows(h);
+      if (rr != BASKER_OK) h->factored = false;
+      return rr;
     }
     h->factored = false;
     if (st[ST_CODE] == DEV_POOL && st[ST_CBPOOL]) {
@@ -950,7 +1003,11 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
     if (r != BASKER_OK) return r;
   }
   h->info.refactor_calls++;
-  if (st[ST_CODE] == DEV_OK) return BASKER_OK;
+  if (st[ST_CODE] == DEV_OK) {
+    r = build_rows(h);
+    if (r != BASKER_OK) h->factored = false;
+    return r;
+  }
   h->info.fail_col = st[ST_FAILCOL] == 0x7fffffff ? -1 : st[ST_FAILCOL];
   if (st[ST_CODE] == DEV_REFACTOR_FAIL || st[ST_CODE] == DEV_WORKSPACE) {
     h->info.refactor_fallbacks++;
@@ -962,11 +1019,9 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
 }
 
 // The task launches of one solve on device-resident B (leading dimension ld) with the
-// work vectors W, Z (n * nrhs doubles each) and the ND node buffers gbuf
-// (s_gbuf_total * nrhs doubles) given by the caller; the status word is the
-// handle's.  Enqueues only: allocates nothing.
-static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int32_t ld, double* W, double* Z,
-                                   double* gbuf) {
+// work vectors W and Z (n * nrhs doubles each) given by the caller; the status word,
+// flags and row-wise factors are the handle's.  Enqueues only: allocates nothing.
+static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int32_t ld, double* W, double* Z) {
   hipStream_t s = h->stream;
   SolveArgs a{};
   a.n = h->plan.n;
@@ -974,17 +1029,15 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   a.ldb = ld;
   a.blkptr = h->blkptr.p;
   a.grpptr = h->grpptr.p;
-  a.st_kind = h->st_kind.p; a.st_id = h->st_id.p; a.st_need = h->st_need.p;
-  a.sg_fd = h->sg_fd.p; a.sg_anc_ptr = h->sg_anc_ptr.p; a.sg_anc = h->sg_anc.p;
-  a.sg_choff = h->sg_choff.p; a.sg_tbase = h->sg_tbase.p; a.rowpos = h->s_rowpos.p;
-  a.gbuf_total = h->plan.s_gbuf_total;
-  a.gbuf = gbuf;
+  a.st_kind = h->st_kind.p; a.st_id = h->st_id.p;
   a.piv = h->piv.p;
-  a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Li = h->Li.p; a.Lx = h->Lx.p;
-  a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
+  a.diag = h->diag.p;
+  a.LTp = h->LTp.p; a.lkeys = h->lkeys_out.p; a.lvals = h->lvals_out.p;
+  a.UTp = h->UTp.p; a.ukeys = h->ukeys_out.p; a.uvals = h->uvals_out.p;
   a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
   a.prow = h->prow.p; a.qcol = h->qcol.p;
   a.B = dB; a.W = W; a.Z = Z;
+  a.sflag = h->sflag.p;
   a.status = h->s_status.p;
   const Plan& P = h->plan;
   const int nsl = (int)P.st_lvl_ptr.size() - 1;
@@ -1007,7 +1060,7 @@ static basker_status finish_solve(basker_ctx* h) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev[2], h->ev[3]) == hipSuccess) h->info.solve_kernel_ms = ms;
-  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve: factor entry outside its block or ND node rows");
+  if (sst != 0) return fail(h, BASKER_ERR_DEVICE, "solve: a row's wait for another row did not end");
   return BASKER_OK;
 }
 
@@ -1031,8 +1084,7 @@ extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, 
     dB = h->Bdev.p;
     ld = n;
   }
-  HIPCHK(h, h->gbuf.reserve(std::max<int64_t>(h->plan.s_gbuf_total * nrhs, 1)));
-  basker_status r = enqueue_solve(h, nrhs, dB, ld, h->W.p, h->Z.p, h->gbuf.p);
+  basker_status r = enqueue_solve(h, nrhs, dB, ld, h->W.p, h->Z.p);
   if (r != BASKER_OK) return r;
   if (!B_on_device)
     HIPCHK(h, hipMemcpy2DAsync(B, sizeof(double) * (size_t)ldb, h->Bdev.p, sizeof(double) * n, sizeof(double) * n,
@@ -1049,12 +1101,12 @@ extern "C" basker_status basker_solve_noalloc(basker_handle h, int32_t nrhs, dou
   double* sp = nullptr;
   HIPCHK(h, noalloc_scratch(h->device, &sp));
   const int64_t n = h->plan.n;
-  const int64_t need = (2 * n + h->plan.s_gbuf_total) * (int64_t)nrhs;
+  const int64_t need = 2 * n * (int64_t)nrhs;
   if (need > kNoAllocScratchDoubles)
     return fail(h, BASKER_ERR_WORKSPACE,
-                "solve needs " + std::to_string(need) + " doubles of scratch (2 n + ND buffers, times nrhs); the "
-                "static scratch holds " + std::to_string(kNoAllocScratchDoubles));
-  basker_status r = enqueue_solve(h, nrhs, B, ldb, sp, sp + n * nrhs, sp + 2 * n * nrhs);
+                "solve needs " + std::to_string(need) + " doubles of scratch (2 n nrhs); the static scratch holds " +
+                    std::to_string(kNoAllocScratchDoubles));
+  basker_status r = enqueue_solve(h, nrhs, B, ldb, sp, sp + n * nrhs);
   if (r != BASKER_OK) return r;
   return finish_solve(h);
 }

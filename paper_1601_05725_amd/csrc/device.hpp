@@ -112,6 +112,29 @@ struct FactorArgs {
   int32_t use_issue;            // 1: take columns from co_issue; 0: in slot order
 };
 
+// row-wise copies of the factors (rows.hip): sort keys and values of the L and U pool
+// extents, the sorted copies, and the row pointers LTp / UTp (n + 1 each)
+struct RowsArgs {
+  int32_t n;
+  const int32_t* pinv;
+  const int32_t* Lbeg; const int32_t* Lcnt; const int32_t* Li; const double* Lx;
+  const int32_t* Ubeg; const int32_t* Ucnt; const int32_t* Ui; const double* Ux;
+  int64_t Lused, Uused;
+  unsigned long long* lkeys; double* lvals; unsigned long long* lkeys_out; double* lvals_out;
+  unsigned long long* ukeys; double* uvals; unsigned long long* ukeys_out; double* uvals_out;
+  void* temp;
+  size_t temp_bytes;
+  int32_t* LTp;
+  int32_t* UTp;
+  double* diag;            // out: U's diagonal (the last entry of every U column)
+};
+
+hipError_t rows_temp_bytes(int64_t items, int n, size_t* bytes);
+hipError_t launch_rows_build(const RowsArgs& a, hipStream_t s);
+
+// solve tasks are workgroups of kSW wavefronts
+constexpr int kSW = 8;
+
 struct SolveArgs {
   int32_t n;
   int32_t nrhs;
@@ -121,30 +144,24 @@ struct SolveArgs {
   // tasks of the launched level: st_*[t_begin .. t_begin + grid)
   const int32_t* st_kind;
   const int32_t* st_id;
-  const int32_t* st_need;  // doubles of work storage; kept in LDS when <= lds_doubles
   int32_t t_begin;
-  int32_t lds_doubles;
-  // ND groups: first descendant, ancestors (root first), ancestor-row offsets, areas
-  const int32_t* sg_fd;
-  const int32_t* sg_anc_ptr;
-  const int32_t* sg_anc;
-  const int32_t* sg_choff;
-  const int64_t* sg_tbase;
-  const int32_t* rowpos;
-  int64_t gbuf_total;      // doubles per right-hand side in gbuf
-  double* gbuf;            // [own rows | ancestor-row buffer] area of every ND group
+  int32_t lds_doubles;     // LDS work vector of the launch: tasks of at most this many rows use it
   const int32_t* piv;
-  const int32_t* Lbeg; const int32_t* Lcnt; const int32_t* Li; const double* Lx;
-  const int32_t* Ubeg; const int32_t* Ucnt; const int32_t* Ui; const double* Ux;
-  const int32_t* OTp;      // off-diagonal part by R row (CSR): columns and values
+  const double* diag;      // U's diagonal by column
+  // row-wise factors: L rows ascending in column, U rows descending (keys: row << 32 |
+  // column, or n - 1 - column for U), first entry of every row
+  const int32_t* LTp; const unsigned long long* lkeys; const double* lvals;
+  const int32_t* UTp; const unsigned long long* ukeys; const double* uvals;
+  const int32_t* OTp;      // off-diagonal part by R row (CSR), later blocks first, columns ascending
   const int32_t* OTj;
   const double* OTx;
   const int32_t* prow;
   const int32_t* qcol;
   double* B;               // in/out, column-major (A numbering)
-  double* W;               // n x nrhs scratch: residual in R-row numbering
-  double* Z;               // n x nrhs scratch: solution in R-column numbering
-  int32_t* status;         // nonzero when an entry falls outside its task's rows
+  double* W;               // n x nrhs: L-solve results (pivot order)
+  double* Z;               // n x nrhs: solution in R-column numbering
+  int32_t* sflag;          // n: done flags of tasks whose rows do not fit in LDS
+  int32_t* status;         // nonzero on a stalled wait
 };
 
 struct DenseSepArgs {

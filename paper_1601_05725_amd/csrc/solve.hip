@@ -1,20 +1,25 @@
-// Solve on gfx950: block back-substitution over the block triangular form.
+// Solve on gfx950: block back-substitution over the block triangular form (Sec. II).
 //
 // R = A(prow, qcol) is block upper triangular, so block b needs the solution of every
 // later block it couples to: r_b = c_b - sum_{c > b} R_bc z_c, then L w = r(piv) and
-// U z_b = w.  The work is cut into tasks (one 64-lane workgroup each) that run in
-// levels, one launch per level:
-//   block task    : one block without an ND tree (residual, L sweep, U sweep);
-//   forward task  : one ND node; its L columns reach its own rows and the rows of its
-//                   ancestors, the latter collected in a per-node buffer that every
-//                   ancestor adds to its own rows, descendants in a fixed order;
-//   backward task : one ND node, root first; it subtracts the products of its rows of
-//                   the ancestors' U columns (a contiguous range, U columns are sorted)
-//                   with the ancestors' solution, then runs its own U sweep.
-// A task keeps its work vectors in LDS when they fit and streams the L and U entries
-// of 64 columns at a time into LDS with one wave-wide gather, so a column step costs
-// LDS latency rather than a global-memory round trip.  Entries are applied column by
-// column in a fixed order, so results do not depend on scheduling.
+// U z_b = w.  The work is cut into tasks that run in levels, one launch per level:
+//   block task    : one block without an ND tree (residual, L rows, U rows);
+//   forward task  : the L rows of one ND node (its rows depend on its own rows and on
+//                   its descendants', which earlier levels finished);
+//   backward task : the U rows of one ND node, root first (its rows depend on its own
+//                   rows and on its ancestors', finished earlier).
+// A task is one workgroup of kSW wavefronts.  The waves take the task's rows round
+// robin in the sweep's order (ascending for L, descending for U), and a row waits only
+// for the rows of the same task it reads (done bits in LDS, release/acquire at
+// workgroup scope); a wave finishes a row before taking its next one, so the first
+// unfinished row can always proceed.
+//
+// Each unknown is computed from one row of the factors, with the updates subtracted
+// one at a time in the order the column sweep applies them: the coupling entries of
+// the row (later blocks first, columns ascending inside a block), then L's entries in
+// ascending column, or U's in descending column, each product rounded and subtracted
+// separately, and z_k = w_k / u_kk.  The result is the column sweep's, bit for bit, and
+// does not depend on the schedule.
 #include "device.hpp"
 
 #include <map>
@@ -22,40 +27,15 @@
 
 namespace basker {
 
-// Work vectors of basker_solve_noalloc: W, Z and the ND node buffers of one solve.
-// Every device the library runs on holds its own copy until the process ends.  Host
-// code never uses this name as an address: noalloc_scratch looks the device address
-// up once per device and every launch takes that pointer.
+// Work vectors of basker_solve_noalloc: W and Z of one solve.  Every device the
+// library runs on holds its own copy until the process ends.  Host code never uses
+// this name as an address: noalloc_scratch looks the device address up once per
+// device and every launch takes that pointer.
 static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
 
 namespace {
 
-constexpr int kStage = 512;   // staged entries per sub-batch
-
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-
-// lanes exchange data through global memory between steps: drain every outstanding
-// memory operation and keep the compiler from moving accesses across
-__device__ __forceinline__ void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
-}
-
-// lanes exchange data through LDS: the LDS unit executes one wave's instructions in
-// issue order, so only the compiler has to be kept from moving accesses across
-__device__ __forceinline__ void lsync() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_wave_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-template <bool kLds>
-__device__ __forceinline__ void step_sync() {
-  if (kLds) lsync(); else wsync();
-}
-
-__device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+constexpr unsigned kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ double rl_d(double v, int l) {
   const long long b = __double_as_longlong(v);
@@ -64,286 +44,223 @@ __device__ __forceinline__ double rl_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ __forceinline__ int wave_excl_scan(int v, int lane) {
-  int x = v;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  return x - v;
+// Ordering between a row's value and its done bit.  In LDS a wavefront's LDS accesses
+// are performed in program order, so only the compiler must keep them in order; in
+// global memory the value is released and acquired at workgroup scope.
+template <bool kLds>
+__device__ __forceinline__ void publish_fence() {
+  if (kLds) __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+}
+template <bool kLds>
+__device__ __forceinline__ void consume_fence() {
+  if (kLds) __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// first position p in [lo, hi) with idx[p] >= key (idx ascending on [lo, hi))
-__device__ __forceinline__ int lower_bound_g(const int32_t* idx, int lo, int hi, int key) {
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (idx[mid] < key) lo = mid + 1; else hi = mid;
+// done bit of task row i: in LDS, or in the global flag array (one word a row)
+template <bool kLds>
+struct Flags {
+  unsigned* lds;       // m bits
+  int32_t* glob;       // the task's rows of the global array
+  __device__ __forceinline__ bool test(int i) const {
+    if (kLds) return (__hip_atomic_load(&lds[i >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> (i & 31)) & 1u;
+    return __hip_atomic_load(&glob[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
   }
-  return lo;
-}
-
-struct Smem {
-  double* sx;      // staged values
-  int32_t* si;     // staged targets (index into the task's work vector)
-  int32_t* pre;    // staged offsets of the sub-batch's columns (65)
-  int32_t* sbeg;   // global start of the sub-batch's columns (64)
-  double* work;    // work vectors when they fit
+  __device__ __forceinline__ void set(int i) const {
+    if (kLds) atomicOr(&lds[i >> 5], 1u << (i & 31));
+    else __hip_atomic_store(&glob[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __device__ __forceinline__ void clear(int m, int tid) const {
+    if (kLds) for (int w = tid; w < ((m + 31) >> 5); w += 64 * kSW) lds[w] = 0u;
+    else for (int i = tid; i < m; i += 64 * kSW) glob[i] = 0;
+  }
 };
 
-// One batch of up to 64 columns, column t of the batch in lane t: its entries are
-// idx/val[beg .. beg+cnt), each applied as S[xf(idx)] -= val * mult(t), columns in
-// lane order.  mult(t) also performs the column's own step (it is called for every
-// column, also one without entries, when all_cols is set).
-template <bool kLds, class Xf, class Mult>
-__device__ __forceinline__ void run_batch(const Smem& sm, double* S, int lane, int nb, int beg, int cnt,
-                                          const int32_t* idx, const double* val, bool all_cols, Xf xf,
-                                          Mult mult) {
-  const int off = wave_excl_scan(lane < nb ? cnt : 0, lane);
-  int j0 = 0;
-  while (j0 < nb) {
-    const int off0 = rl(off, j0);
-    const bool fit = lane >= j0 && lane < nb && off + cnt - off0 <= kStage;
-    const int nfit = __popcll(__ballot(fit));
-    if (nfit == 0) {
-      // a column with more entries than the stage holds: straight from global memory
-      const int c = rl(cnt, j0), b = rl(beg, j0);
-      const double m = mult(j0);
-      for (int e = lane; e < c; e += 64) {
-        const int t = xf(idx[b + e]);
-        const double x = val[b + e];
-        if (t >= 0) S[t] = S[t] - x * m;
+// acc - sum over entries, one at a time in entry order: lanes hold up to 64 products
+__device__ __forceinline__ double subtract_in_order(double acc, double prod, int cnt) {
+  for (int t = 0; t < cnt; t++) acc = acc - rl_d(prod, t);
+  return acc;
+}
+
+// The first (up to) 64 entries of a sorted factor row, loaded ahead of their use: the
+// lane's column and value, and the row's entry range.
+struct RowPre {
+  int e0, e1;
+  int j;
+  double x;
+};
+
+// ptr: the task's slice of the row pointers (in LDS, or global for tasks beyond LDS),
+// kk the task-local row
+__device__ __forceinline__ void row_prefetch(RowPre& r, const int32_t* ptr, const unsigned long long* keys,
+                                             const double* vals, int kk, bool rev, int n, int lane) {
+  r.e0 = ptr[kk];
+  r.e1 = ptr[kk + 1];
+  r.j = -1;
+  r.x = 0.0;
+  if (lane < r.e1 - r.e0) {
+    const unsigned lo = (unsigned)keys[r.e0 + lane];
+    r.j = rev ? n - 1 - (int)lo : (int)lo;
+    r.x = vals[r.e0 + lane];
+  }
+}
+
+// Subtract a sorted factor row from acc: columns inside the task's rows [r0, r0 + m)
+// are read from V after their done bits, any other column is final and read from `fin`.
+// Returns false on a stall.
+template <bool kLds>
+__device__ __forceinline__ bool row_update(double& acc, const RowPre& r, const unsigned long long* keys,
+                                           const double* vals, bool rev, int n, int r0, int m, const double* V,
+                                           const Flags<kLds>& F, const double* fin, int lane) {
+  bool stalled = false;
+  for (int b = r.e0; b < r.e1; b += 64) {
+    const int cnt = (r.e1 - b < 64) ? r.e1 - b : 64;
+    int j = r.j;
+    double x = r.x;
+    if (b != r.e0) {
+      j = -1;
+      if (lane < cnt) {
+        const unsigned lo = (unsigned)keys[b + lane];
+        j = rev ? n - 1 - (int)lo : (int)lo;
+        x = vals[b + lane];
       }
-      step_sync<kLds>();
-      j0++;
-      continue;
     }
-    const int j1 = j0 + nfit;
-    // stage the entries of columns [j0, j1)
-    if (lane >= j0 && lane < j1) {
-      sm.pre[lane - j0] = off - off0;
-      sm.sbeg[lane - j0] = beg;
-    }
-    if (lane == j1 - 1) sm.pre[j1 - j0] = off + cnt - off0;
-    lsync();
-    const int total = rl(off, j1 - 1) + rl(cnt, j1 - 1) - off0;
-    const int nc = j1 - j0;
-    for (int base = 0; base < total; base += 64 * 8) {
-      int gi[8];
-#pragma unroll
-      for (int u = 0; u < 8; u++) {
-        const int s = base + u * 64 + lane;
-        gi[u] = -1;
-        if (s < total) {
-          int lo = 0, hi = nc;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (sm.pre[mid] <= s) lo = mid; else hi = mid;
-          }
-          gi[u] = sm.sbeg[lo] + (s - sm.pre[lo]);
+    double prod = 0.0;
+    if (lane < cnt) {
+      double v;
+      const int jj = j - r0;
+      if (jj >= 0 && jj < m) {
+        unsigned spins = 0;
+        while (!F.test(jj)) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) { stalled = true; break; }
         }
+        consume_fence<kLds>();
+        v = V[jj];
+      } else {
+        v = fin[j];
       }
-      int32_t ri[8];
-      double rx[8];
-#pragma unroll
-      for (int u = 0; u < 8; u++) {
-        ri[u] = 0;
-        rx[u] = 0.0;
-        if (gi[u] >= 0) { ri[u] = idx[gi[u]]; rx[u] = val[gi[u]]; }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; u++) {
-        const int s = base + u * 64 + lane;
-        if (gi[u] >= 0) { sm.si[s] = xf(ri[u]); sm.sx[s] = rx[u]; }
-      }
+      prod = x * v;
     }
-    lsync();
-    // apply, column by column
-    for (int j = j0; j < j1; j++) {
-      const int c = rl(cnt, j);
-      if (c == 0 && !all_cols) continue;
-      const int o = rl(off, j) - off0;
-      const double m = mult(j);
-      for (int e = lane; e < c; e += 64) {
-        const int t = sm.si[o + e];
-        const double x = sm.sx[o + e];
-        if (t >= 0) S[t] = S[t] - x * m;
-      }
-      step_sync<kLds>();
-    }
-    j0 = j1;
+    acc = subtract_in_order(acc, prod, cnt);
   }
-}
-
-// residual of rows [r0, r0 + m): S[i] = B(prow[r0+i]) - sum_c R(r0+i, c) z_c
-template <bool kLds>
-__device__ void residual_rows(const SolveArgs& a, double* S, int r0, int m, const double* Bc, const double* Z,
-                              int lane) {
-  for (int i = lane; i < m; i += 64) {
-    const int r = r0 + i;
-    double v = Bc[a.prow[r]];
-    for (int q = a.OTp[r]; q < a.OTp[r + 1]; q++) {
-      const double prod = a.OTx[q] * Z[a.OTj[q]];
-      v = v - prod;
-    }
-    S[i] = v;
-  }
-  step_sync<kLds>();
-}
-
-// L sweep over columns [c0, c1) (rows of the task start at c0); the pivot rows are
-// own rows.  xf maps an L row to its slot in S.
-template <bool kLds, class Xf>
-__device__ void l_sweep(const SolveArgs& a, const Smem& sm, double* S, int c0, int c1, int lane, Xf xf) {
-  for (int kb = c0; kb < c1; kb += 64) {
-    const int nb = c1 - kb < 64 ? c1 - kb : 64;
-    int beg = 0, cnt = 0, pv = 0;
-    if (lane < nb) {
-      const int k = kb + lane;
-      beg = a.Lbeg[k];
-      cnt = a.Lcnt[k];
-      pv = a.piv[k] - c0;
-    }
-    run_batch<kLds>(sm, S, lane, nb, beg, cnt, a.Li, a.Lx, false, xf,
-                    [&](int j) -> double { return S[rl(pv, j)]; });
-  }
-}
-
-// U sweep over columns [c0, c1), last first; entries with rows below c0 belong to
-// descendants and are skipped (search set) or absent (block task)
-template <bool kLds>
-__device__ void u_sweep(const SolveArgs& a, const Smem& sm, double* S, int c0, int c1, int lane, bool search) {
-  for (int kb = c1; kb > c0; kb -= 64) {
-    const int nb = kb - c0 < 64 ? kb - c0 : 64;
-    int beg = 0, cnt = 0, kl = 0;
-    double d = 1.0;
-    if (lane < nb) {
-      const int k = kb - 1 - lane;
-      const int b = a.Ubeg[k], ca = a.Ucnt[k];
-      d = a.Ux[b + ca - 1];
-      beg = search ? lower_bound_g(a.Ui, b, b + ca - 1, c0) : b;
-      cnt = b + ca - 1 - beg;
-      kl = k - c0;
-    }
-    run_batch<kLds>(sm, S, lane, nb, beg, cnt, a.Ui, a.Ux, true, [&](int j) { return j - c0; },
-                    [&](int j) -> double {
-                      const int kk = rl(kl, j);
-                      const double zk = S[kk] / rl_d(d, j);
-                      step_sync<kLds>();
-                      if (lane == 0) S[kk] = zk;
-                      return zk;
-                    });
-  }
+  return !__any(stalled);
 }
 
 template <bool kLds>
-__device__ void block_task(const SolveArgs& a, const Smem& sm, int b, int rhs, int lane) {
-  const int b0 = a.blkptr[b], b1 = a.blkptr[b + 1], m = b1 - b0;
-  double* Z = a.Z + (int64_t)rhs * a.n;
+__device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, const Flags<kLds>& F, int kind, int id, int rhs,
+                         int tid) {
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  int r0, r1;
+  if (kind == 0) { r0 = a.blkptr[id]; r1 = a.blkptr[id + 1]; }
+  else { r0 = a.grpptr[id]; r1 = a.grpptr[id + 1]; }
+  const int m = r1 - r0;
+  const int n = a.n;
+  double* W = a.W + (int64_t)rhs * n;
+  double* Z = a.Z + (int64_t)rhs * n;
   const double* Bc = a.B + (int64_t)rhs * a.ldb;
-  double* Wl = kLds ? sm.work : a.W + (int64_t)rhs * a.n + b0;
-  double* Zl = kLds ? sm.work + m : Z + b0;
-  residual_rows<kLds>(a, Wl, b0, m, Bc, Z, lane);
-  int32_t* status = a.status;
-  l_sweep<kLds>(a, sm, Wl, b0, b1, lane, [&](int r) {
-    const int t = r - b0;
-    if ((unsigned)t >= (unsigned)m) { atomicOr(status, 1); return -1; }
-    return t;
-  });
-  for (int k = lane; k < m; k += 64) Zl[k] = Wl[a.piv[b0 + k] - b0];
-  step_sync<kLds>();
-  u_sweep<kLds>(a, sm, Zl, b0, b1, lane, false);
-  if (kLds) {
-    for (int k = lane; k < m; k += 64) Z[b0 + k] = Zl[k];
-  }
-}
-
-template <bool kLds>
-__device__ void nd_forward_task(const SolveArgs& a, const Smem& sm, int g, int rhs, int lane) {
-  const int c0 = a.grpptr[g], c1 = a.grpptr[g + 1], m = c1 - c0;
-  const int choff = a.sg_choff[g];
-  double* Z = a.Z + (int64_t)rhs * a.n;
-  const double* Bc = a.B + (int64_t)rhs * a.ldb;
-  double* gb = a.gbuf + (int64_t)rhs * a.gbuf_total;
-  double* S = kLds ? sm.work : gb + a.sg_tbase[g];
-  residual_rows<kLds>(a, S, c0, m, Bc, Z, lane);
-  for (int p = lane; p < choff; p += 64) S[m + p] = 0.0;
-  // buffers of the descendants (postorder: groups [fd, g)), lowest first
-  for (int d = a.sg_fd[g]; d < g; d++) {
-    const double* bd = gb + a.sg_tbase[d] + (a.grpptr[d + 1] - a.grpptr[d]) + choff;
-    for (int i = lane; i < m; i += 64) S[i] = S[i] + bd[i];
-  }
-  step_sync<kLds>();
-  const int32_t* rowpos = a.rowpos;
-  int32_t* status = a.status;
-  l_sweep<kLds>(a, sm, S, c0, c1, lane, [&](int r) {
-    const int t = r - c0;
-    if ((unsigned)t < (unsigned)m) return t;
-    const int p = rowpos[r];
-    if (p < 0 || p >= choff) { atomicOr(status, 2); return -1; }
-    return m + p;
-  });
-  for (int k = lane; k < m; k += 64) Z[c0 + k] = S[a.piv[c0 + k] - c0];
-  if (kLds) {
-    double* out = gb + a.sg_tbase[g] + m;
-    for (int p = lane; p < choff; p += 64) out[p] = S[m + p];
-  }
-}
-
-template <bool kLds>
-__device__ void nd_backward_task(const SolveArgs& a, const Smem& sm, int g, int rhs, int lane) {
-  const int c0 = a.grpptr[g], c1 = a.grpptr[g + 1], m = c1 - c0;
-  double* Z = a.Z + (int64_t)rhs * a.n;
-  double* S = kLds ? sm.work : Z + c0;
-  if (kLds) {
-    for (int i = lane; i < m; i += 64) S[i] = Z[c0 + i];
-    lsync();
-  }
-  // ancestors' columns, last first: rows [c0, c1) of each column
-  for (int q = a.sg_anc_ptr[g + 1] - 1; q >= a.sg_anc_ptr[g]; q--) {
-    const int an = a.sg_anc[q];
-    const int a0 = a.grpptr[an], a1 = a.grpptr[an + 1];
-    for (int kb = a1; kb > a0; kb -= 64) {
-      const int nb = kb - a0 < 64 ? kb - a0 : 64;
-      int beg = 0, cnt = 0;
-      double zk = 0.0;
-      if (lane < nb) {
-        const int k = kb - 1 - lane;
-        const int b = a.Ubeg[k], e = b + a.Ucnt[k] - 1;
-        beg = lower_bound_g(a.Ui, b, e, c0);
-        cnt = lower_bound_g(a.Ui, beg, e, c1) - beg;
-        zk = Z[k];
+  bool ok = true;
+  if (kind != 2) {
+    // residual of every row (independent of the task's other rows): the right-hand
+    // side minus the coupling to finished later blocks, in the sweep's order
+    F.clear(m, tid);
+    for (int kk = tid; kk < m; kk += 64 * kSW) {
+      const int i = a.piv[r0 + kk];
+      double acc = Bc[a.prow[i]];
+      for (int q = a.OTp[i]; q < a.OTp[i + 1]; q++) {
+        const double prod = a.OTx[q] * Z[a.OTj[q]];
+        acc = acc - prod;
       }
-      run_batch<kLds>(sm, S, lane, nb, beg, cnt, a.Ui, a.Ux, false, [&](int j) { return j - c0; },
-                      [&](int j) -> double { return rl_d(zk, j); });
+      V[kk] = acc;
+    }
+    // the task's L row pointers
+    const int32_t* LP = a.LTp + r0;
+    if (kLds) {
+      for (int kk = tid; kk <= m; kk += 64 * kSW) Pl[kk] = a.LTp[r0 + kk];
+      LP = Pl;
+    }
+    __syncthreads();
+    // L rows, ascending
+    RowPre cur, nxt;
+    if (wv < m) row_prefetch(cur, LP, a.lkeys, a.lvals, wv, false, n, lane);
+    for (int kk = wv; kk < m; kk += kSW) {
+      if (kk + kSW < m) row_prefetch(nxt, LP, a.lkeys, a.lvals, kk + kSW, false, n, lane);
+      double acc = V[kk];
+      ok &= row_update<kLds>(acc, cur, a.lkeys, a.lvals, false, n, r0, m, V, F, W, lane);
+      if (lane == 0) V[kk] = acc;
+      publish_fence<kLds>();
+      if (lane == 0) F.set(kk);
+      cur = nxt;
+    }
+    __syncthreads();
+    if (kind == 1) {
+      for (int kk = tid; kk < m; kk += 64 * kSW) W[r0 + kk] = V[kk];
+      if (!ok && tid == 0) atomicOr(a.status, 4);
+      return;
+    }
+  } else {
+    for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = W[r0 + kk];
+  }
+  // U rows, descending: z_k = (w_k - sum_{j > k} u_kj z_j) / u_kk
+  F.clear(m, tid);
+  __syncthreads();
+  const int32_t* UP = a.UTp + r0;
+  if (kLds) {
+    for (int kk = tid; kk <= m; kk += 64 * kSW) Pl[kk] = a.UTp[r0 + kk];
+    UP = Pl;
+  }
+  __syncthreads();
+  {
+    RowPre cur, nxt;
+    double dcur = 1.0, dnxt = 1.0;
+    if (wv < m) {
+      row_prefetch(cur, UP, a.ukeys, a.uvals, m - 1 - wv, true, n, lane);
+      dcur = a.diag[r1 - 1 - wv];
+    }
+    for (int q = wv; q < m; q += kSW) {
+      const int kk = m - 1 - q;
+      if (q + kSW < m) {
+        row_prefetch(nxt, UP, a.ukeys, a.uvals, kk - kSW, true, n, lane);
+        dnxt = a.diag[r0 + kk - kSW];
+      }
+      double acc = V[kk];
+      ok &= row_update<kLds>(acc, cur, a.ukeys, a.uvals, true, n, r0, m, V, F, Z, lane);
+      const double z = acc / dcur;
+      if (lane == 0) V[kk] = z;
+      publish_fence<kLds>();
+      if (lane == 0) F.set(kk);
+      cur = nxt;
+      dcur = dnxt;
     }
   }
-  u_sweep<kLds>(a, sm, S, c0, c1, lane, true);
-  if (kLds) {
-    for (int i = lane; i < m; i += 64) Z[c0 + i] = S[i];
-  }
+  __syncthreads();
+  for (int kk = tid; kk < m; kk += 64 * kSW) Z[r0 + kk] = V[kk];
+  if (!ok && tid == 0) atomicOr(a.status, 4);
 }
 
-__global__ void __launch_bounds__(64) solve_task_kernel(SolveArgs a) {
+__global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
   BASKER_DYN_SHARED(double, smem_d);
-  const int lane = lane_id();
-  Smem sm;
-  sm.sx = smem_d;
-  sm.work = smem_d + kStage;
-  sm.si = reinterpret_cast<int32_t*>(smem_d + kStage + a.lds_doubles);
-  sm.pre = sm.si + kStage;
-  sm.sbeg = sm.pre + 72;
+  const int tid = threadIdx.x;
   const int t = a.t_begin + (int)blockIdx.x;
   const int kind = a.st_kind[t], id = a.st_id[t];
-  const bool lds = a.st_need[t] <= a.lds_doubles;
+  const int m = kind == 0 ? a.blkptr[id + 1] - a.blkptr[id] : a.grpptr[id + 1] - a.grpptr[id];
+  const bool lds = m <= a.lds_doubles;
   for (int rhs = 0; rhs < a.nrhs; rhs++) {
-    if (kind == 0) {
-      if (lds) block_task<true>(a, sm, id, rhs, lane); else block_task<false>(a, sm, id, rhs, lane);
-    } else if (kind == 1) {
-      if (lds) nd_forward_task<true>(a, sm, id, rhs, lane); else nd_forward_task<false>(a, sm, id, rhs, lane);
+    if (lds) {
+      // LDS: work vector (lds_doubles), row pointers (lds_doubles + 1), done bits
+      int32_t* Pl = reinterpret_cast<int32_t*>(smem_d + a.lds_doubles);
+      Flags<true> F{reinterpret_cast<unsigned*>(Pl + a.lds_doubles + 1), nullptr};
+      run_task<true>(a, smem_d, Pl, F, kind, id, rhs, tid);
     } else {
-      if (lds) nd_backward_task<true>(a, sm, id, rhs, lane); else nd_backward_task<false>(a, sm, id, rhs, lane);
+      const int r0 = kind == 0 ? a.blkptr[id] : a.grpptr[id];
+      Flags<false> F{nullptr, a.sflag + r0};
+      // work vector in place: the block's (or node's) part of Z, or of W for a forward task
+      double* V = (kind == 1 ? a.W : a.Z) + (int64_t)rhs * a.n + r0;
+      run_task<false>(a, V, nullptr, F, kind, id, rhs, tid);
     }
-    wsync();
+    __syncthreads();
   }
 }
 
@@ -360,7 +277,8 @@ __global__ void solve_unpermute_kernel(SolveArgs a) {
 }  // namespace
 
 size_t solve_lds_bytes(int32_t work_doubles) {
-  return sizeof(double) * ((size_t)kStage + (size_t)work_doubles) + sizeof(int32_t) * ((size_t)kStage + 72 + 64);
+  return sizeof(double) * (size_t)work_doubles + sizeof(int32_t) * ((size_t)work_doubles + 1) +
+         sizeof(unsigned) * (((size_t)work_doubles + 31) / 32 + 1);
 }
 
 hipError_t solve_lds_setup(size_t max_bytes) {
@@ -370,7 +288,7 @@ hipError_t solve_lds_setup(size_t max_bytes) {
 
 hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s) {
   if (ntasks > 0)
-    hipLaunchKernelGGL(solve_task_kernel, dim3(ntasks), dim3(64), solve_lds_bytes(a.lds_doubles), s, a);
+    hipLaunchKernelGGL(solve_task_kernel, dim3(ntasks), dim3(64 * kSW), solve_lds_bytes(a.lds_doubles), s, a);
   return hipGetLastError();
 }
 

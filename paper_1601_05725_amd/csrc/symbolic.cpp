@@ -955,9 +955,8 @@ void build_solve_tasks(Plan& P) {
     P.st_kind[q] = kind[t];
     P.st_id[q] = id[t];
     const int m = tsize(t);
-    // doubles of work storage: block: residual/L part and U part; forward node: own
-    // rows and the ancestor-row buffer; backward node: own rows
-    P.st_need[q] = kind[t] == 0 ? 2 * m : kind[t] == 1 ? m + P.sg_choff[id[t]] : m;
+    // doubles of work storage: the task's rows
+    P.st_need[q] = m;
   }
 }
 
