@@ -259,7 +259,8 @@ def main():
         "refactor_fallbacks": info["refactor_fallbacks"],
         "schedule": {"first_level_items": info["coop_items"], "waves_per_workgroup": info["coop_waves"],
                      "redo_items_last": info["redo_items"], "learn_events": info["learn_events"],
-                     "dense_separators": info["dense_seps"], "pool_regrows": info["pool_regrows"]},
+                     "dense_separators": info["dense_seps"], "pool_regrows": info["pool_regrows"],
+                     "solve_levels": info["solve_levels"], "solve_order_fallbacks": info["solve_order_fallbacks"]},
         "solve_kernel_ms": float(np.mean(sk)),
         "scatter_kernel_ms": float(np.mean(sc)),
         "hbm_gbs_factor": achieved,

@@ -119,7 +119,8 @@ typedef struct {
   int32_t coop_waves;        /* wavefronts per first-level workgroup */
   int32_t redo_items;        /* first-level items the last factorization redid after a failed speculation */
   int32_t learn_events;      /* factorizations whose observed dependencies were merged into the schedule */
-  int32_t reserved0;
+  int32_t solve_order_fallbacks; /* solve sweeps of first-level tasks (forward or backward) that the
+                                    check after the last factorization sent back to plain row order */
   double rows_kernel_ms;     /* device time of the row-wise copies of L and U built after the last
                                 successful factor/refactor (used by the solve) */
 } basker_info_t;

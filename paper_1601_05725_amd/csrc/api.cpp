@@ -97,11 +97,11 @@ struct basker_ctx {
   int coop_grid = 0;
   // solve tasks, row-wise factors (rebuilt after every factorization), done flags
   DBuf<int32_t> st_kind, st_id, s_status, sflag, LTp, UTp;
+  DBuf<int32_t> sfo, sbo, sfo_pos, sbo_pos, row_task0, obad, ocount;   // solve issue orders and their check
   DBuf<unsigned long long> lkeys, lkeys_out, ukeys, ukeys_out;
   DBuf<double> lvals, lvals_out, uvals, uvals_out, diag;
   DBuf<char> rows_temp;
-  std::vector<int32_t> st_lvl_lds;   // LDS work doubles of every solve level
-  int32_t solve_lds_cap = 0;
+  std::vector<int32_t> st_lvl_lds;   // LDS bytes of every solve level's launch
   // numeric state
   DBuf<double> vals, Rx, OTx;
   DBuf<int32_t> pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
@@ -349,6 +349,8 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(4, n); add(4, n); add(4, nb + 1); add(4, ng + 1);            // prow, qcol, blkptr, grpptr
   add(4, nt); add(4, nt); add(4, 1); add(4, n); add(4, n + 1); add(4, n + 1);   // tasks, status, flags, row pointers
   add(8, n);                                                                     // U's diagonal
+  for (int t = 0; t < 6; t++) add(4, n);                                         // solve issue orders
+  add(4, 1);
   add(8, P.nnz); add(8, nnzd); add(8, nnzo);                       // vals, Rx, OTx
   for (int t = 0; t < 6; t++) add(4, n);                           // pinv, piv, Lbeg..Ucnt
   add(4, kStatusWords); add(8, 3);
@@ -372,11 +374,33 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
 
 // Everything the device needs from the plan, plus the solve's row-wise coupling and
 // block dependency lists.
+// The solve kernel takes each task's rows from its issue orders: every task's slice of
+// sfo and sbo must list exactly the task's rows, with *_pos the inverse.
+static bool solve_orders_valid(const Plan& P) {
+  const int n = P.n;
+  if ((int)P.sfo.size() != n || (int)P.sbo.size() != n || (int)P.sfo_pos.size() != n ||
+      (int)P.sbo_pos.size() != n || (int)P.row_task0.size() != n)
+    return false;
+  for (int k = 0; k < n; k++) {
+    const int t0 = P.row_task0[k];
+    if (t0 < 0 || t0 > k || P.row_task0[t0] != t0) return false;
+    const int f = P.sfo[k], b = P.sbo[k];
+    if (f < 0 || f >= n || b < 0 || b >= n || P.row_task0[f] != t0 || P.row_task0[b] != t0) return false;
+    if (P.sfo_pos[f] != k - t0 || P.sbo_pos[b] != k - t0) return false;
+  }
+  return true;
+}
+
 static basker_status upload_plan(basker_ctx* h) {
   AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
   Plan& P = h->plan;
   const int n = P.n;
   hipStream_t s = h->stream;
+  if (!solve_orders_valid(P)) {
+    P.sfo.clear();
+    build_solve_orders(P, nullptr, false);
+    if (!solve_orders_valid(P)) return fail(h, BASKER_ERR_INVALID, "solve issue orders");
+  }
   std::vector<int32_t> glo(n), ghi(n);
   for (size_t g = 0; g + 1 < P.grpptr.size(); g++)
     for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) { glo[k] = P.grpptr[g]; ghi[k] = P.grpptr[g + 1]; }
@@ -441,23 +465,36 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->LTp.reserve(n + 1));
   HIPCHK(h, h->UTp.reserve(n + 1));
   HIPCHK(h, h->diag.reserve(n));
+  HIPCHK(h, h->sfo.upload(P.sfo, s));
+  HIPCHK(h, h->sbo.upload(P.sbo, s));
+  HIPCHK(h, h->sfo_pos.upload(P.sfo_pos, s));
+  HIPCHK(h, h->sbo_pos.upload(P.sbo_pos, s));
+  HIPCHK(h, h->row_task0.upload(P.row_task0, s));
+  HIPCHK(h, h->obad.reserve(n));
+  HIPCHK(h, h->ocount.reserve(1));
   {
-    // LDS per solve launch: the largest work area of the level that fits the device
-    int lds_max = 0;
+    // LDS per solve launch: the device's whole workgroup LDS when the level has no more
+    // tasks than compute units (one task per CU, so the rows' entries can be staged), else
+    // what the level's largest task that fits needs, so several tasks share a CU
+    int lds_max = 0, ncu = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess)
       lds_max = 65536;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
     lds_max = std::min(lds_max, 160 * 1024);
     if (lds_max > 65536 && solve_lds_setup((size_t)lds_max) != hipSuccess) lds_max = 65536;
     (void)hipGetLastError();
     HIPCHK(h, sepdense_setup());
-    int32_t cap = (int32_t)((size_t)lds_max / sizeof(double));
-    while (cap > 0 && solve_lds_bytes(cap) > (size_t)lds_max) cap--;
-    h->solve_lds_cap = cap;
     const int nsl = (int)P.st_lvl_ptr.size() - 1;
     h->st_lvl_lds.assign(std::max(nsl, 0), 0);
-    for (int l = 0; l < nsl; l++)
-      for (int t = P.st_lvl_ptr[l]; t < P.st_lvl_ptr[l + 1]; t++)
-        if (P.st_need[t] <= h->solve_lds_cap) h->st_lvl_lds[l] = std::max(h->st_lvl_lds[l], P.st_need[t]);
+    for (int l = 0; l < nsl; l++) {
+      const int nt = P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l];
+      size_t need = solve_lds_bytes(0);
+      for (int t = P.st_lvl_ptr[l]; t < P.st_lvl_ptr[l + 1]; t++) {
+        const size_t b = solve_lds_bytes(P.st_need[t]);
+        if (b <= (size_t)lds_max) need = std::max(need, b);
+      }
+      h->st_lvl_lds[l] = nt <= ncu ? lds_max : (int32_t)std::min<size_t>(need, (size_t)lds_max);
+    }
   }
   const int64_t nnzd = (int64_t)P.Ri.size();
   HIPCHK(h, h->vals.reserve(P.nnz));
@@ -849,10 +886,16 @@ static basker_status build_rows(basker_ctx* h) {
   r.temp_bytes = (size_t)h->rows_temp.cap;
   r.LTp = h->LTp.p; r.UTp = h->UTp.p;
   r.diag = h->diag.p;
+  r.row_task0 = h->row_task0.p; r.sfo_pos = h->sfo_pos.p; r.sbo_pos = h->sbo_pos.p;
+  r.obad = h->obad.p;
+  r.ocount = h->ocount.p;
   HIPCHK(h, hipEventRecord(h->ev[4], s));
   HIPCHK(h, launch_rows_build(r, s));
   HIPCHK(h, hipEventRecord(h->ev[5], s));
+  int32_t fallbacks = 0;
+  HIPCHK(h, hipMemcpyAsync(&fallbacks, h->ocount.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  h->info.solve_order_fallbacks = fallbacks;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev[4], h->ev[5]) == hipSuccess) h->info.rows_kernel_ms = ms;
   return BASKER_OK;
@@ -882,6 +925,8 @@ static basker_status learn_deps(basker_ctx* h) {
   HIPCHK(h, h->dep_ptr.upload(P.dep_ptr, s));
   HIPCHK(h, h->dep_idx.upload(P.dep_idx, s));
   HIPCHK(h, h->co_issue.upload(P.co_issue, s));
+  HIPCHK(h, h->sbo.upload(P.sbo, s));
+  HIPCHK(h, h->sbo_pos.upload(P.sbo_pos, s));
   HIPCHK(h, hipStreamSynchronize(s));
   h->info.learn_events++;
   return BASKER_OK;
@@ -1035,6 +1080,7 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   a.LTp = h->LTp.p; a.lkeys = h->lkeys_out.p; a.lvals = h->lvals_out.p;
   a.UTp = h->UTp.p; a.ukeys = h->ukeys_out.p; a.uvals = h->uvals_out.p;
   a.OTp = h->OTp.p; a.OTj = h->OTj.p; a.OTx = h->OTx.p;
+  a.sfo = h->sfo.p; a.sbo = h->sbo.p; a.obad = h->obad.p;
   a.prow = h->prow.p; a.qcol = h->qcol.p;
   a.B = dB; a.W = W; a.Z = Z;
   a.sflag = h->sflag.p;
@@ -1045,7 +1091,7 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   HIPCHK(h, hipEventRecord(h->ev[2], s));
   for (int l = 0; l < nsl; l++) {
     a.t_begin = P.st_lvl_ptr[l];
-    a.lds_doubles = h->st_lvl_lds[l];
+    a.lds_bytes = h->st_lvl_lds[l];
     HIPCHK(h, launch_solve_tasks(a, P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l], s));
   }
   HIPCHK(h, launch_solve_finish(a, s));

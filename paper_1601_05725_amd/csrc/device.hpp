@@ -127,6 +127,14 @@ struct RowsArgs {
   int32_t* LTp;
   int32_t* UTp;
   double* diag;            // out: U's diagonal (the last entry of every U column)
+  // solve issue orders to check against the rows: the first row of every row's solve
+  // task, each row's rank in its task's forward and backward orders; out: per task
+  // (indexed by its first row) bit 0 = forward order invalid, bit 1 = backward
+  const int32_t* row_task0;
+  const int32_t* sfo_pos;
+  const int32_t* sbo_pos;
+  int32_t* obad;
+  int32_t* ocount;         // out: sweeps found invalid (one word)
 };
 
 hipError_t rows_temp_bytes(int64_t items, int n, size_t* bytes);
@@ -145,13 +153,19 @@ struct SolveArgs {
   const int32_t* st_kind;
   const int32_t* st_id;
   int32_t t_begin;
-  int32_t lds_doubles;     // LDS work vector of the launch: tasks of at most this many rows use it
+  int32_t lds_bytes;       // dynamic LDS of the launch; a task whose rows' work arrays fit runs in it
   const int32_t* piv;
   const double* diag;      // U's diagonal by column
   // row-wise factors: L rows ascending in column, U rows descending (keys: row << 32 |
   // column, or n - 1 - column for U), first entry of every row
   const int32_t* LTp; const unsigned long long* lkeys; const double* lvals;
   const int32_t* UTp; const unsigned long long* ukeys; const double* uvals;
+  // issue orders: the rows of every task in the order its wavefronts take them
+  // (sfo forward, sbo backward, at the task's first row), used where `obad` of the task
+  // has the sweep's bit clear
+  const int32_t* sfo;
+  const int32_t* sbo;
+  const int32_t* obad;
   const int32_t* OTp;      // off-diagonal part by R row (CSR), later blocks first, columns ascending
   const int32_t* OTj;
   const double* OTx;
@@ -215,7 +229,7 @@ hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, hipStream_t s)
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);
-size_t solve_lds_bytes(int32_t work_doubles);
+size_t solve_lds_bytes(int32_t rows);   // LDS a task of `rows` rows needs
 hipError_t solve_lds_setup(size_t max_bytes);
 hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s);
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s);

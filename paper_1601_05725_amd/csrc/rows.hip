@@ -8,7 +8,8 @@
 // (row << 32 | column) per entry of the pools (or the reversed column for U), a radix
 // sort of (key, value) pairs, and the first entry of every row found by binary search.
 // Pool slots between the columns' chunks, and U's diagonal entries, get the largest
-// key and sort to the end.
+// key and sort to the end.  Last, the solve's issue orders are checked against the
+// rows' actual patterns.
 #include <hipcub/hipcub.hpp>
 
 #include "device.hpp"
@@ -57,6 +58,39 @@ __global__ void row_ptr_kernel(const unsigned long long* keys, int64_t cnt, int3
     if (keys[mid] < key) lo = mid + 1; else hi = mid;
   }
   ptr[k] = (int32_t)lo;
+}
+
+__global__ void clear_order_flags_kernel(int32_t* x, int n, int32_t* count) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) x[i] = 0;
+  if (i == 0) *count = 0;
+}
+
+// one wavefront per row k: an issue order is valid when every entry of the row in
+// another row of the same task comes earlier in the task's order (then the first
+// unfinished row in the order can always proceed)
+__global__ void order_check_kernel(RowsArgs a) {
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (gw >= a.n) return;
+  const int k = (int)gw;
+  const int t0 = a.row_task0[k];
+  bool badf = false, badb = false;
+  for (int p = a.LTp[k] + lane; p < a.LTp[k + 1]; p += 64) {
+    const int j = (int)(unsigned)a.lkeys_out[p];
+    badf |= a.row_task0[j] == t0 && a.sfo_pos[j] >= a.sfo_pos[k];
+  }
+  for (int p = a.UTp[k] + lane; p < a.UTp[k + 1]; p += 64) {
+    const int j = a.n - 1 - (int)(unsigned)a.ukeys_out[p];
+    badb |= a.row_task0[j] == t0 && a.sbo_pos[j] >= a.sbo_pos[k];
+  }
+  const bool f = __any(badf), b = __any(badb);
+  if (lane == 0 && (f || b)) {
+    const int bits = (f ? 1 : 0) | (b ? 2 : 0);
+    const int old = atomicOr(&a.obad[t0], bits);
+    const int fresh = bits & ~old;
+    if (fresh) atomicAdd(a.ocount, __popc(fresh));
+  }
 }
 
 int key_bits(int n) {
@@ -108,6 +142,11 @@ hipError_t launch_rows_build(const RowsArgs& a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(row_ptr_kernel, dim3((unsigned)((a.n + 1 + 255) / 256)), dim3(256), 0, s,
                      (const unsigned long long*)a.ukeys_out, a.Uused, a.UTp, a.n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(clear_order_flags_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.obad, a.n,
+                     a.ocount);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(order_check_kernel, dim3((unsigned)(((int64_t)a.n * 64 + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

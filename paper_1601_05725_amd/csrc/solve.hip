@@ -9,10 +9,14 @@
 //   backward task : the U rows of one ND node, root first (its rows depend on its own
 //                   rows and on its ancestors', finished earlier).
 // A task is one workgroup of kSW wavefronts.  The waves take the task's rows round
-// robin in the sweep's order (ascending for L, descending for U), and a row waits only
-// for the rows of the same task it reads (done bits in LDS, release/acquire at
-// workgroup scope); a wave finishes a row before taking its next one, so the first
-// unfinished row can always proceed.
+// robin in an issue order, and a row waits only for the rows of the same task it reads
+// (done bits in LDS, release/acquire at workgroup scope).  The issue order of a
+// first-level task lists its rows by levels of the predicted dependency graph (rows
+// with no dependency inside the task first), so independent rows do not queue behind
+// a chain; after every factorization a check against the actual rows keeps an order
+// only where every row's dependencies come before it, else the sweep's own order
+// (ascending for L, descending for U) is used.  Either way a wave finishes a row before
+// taking its next one and the first unfinished row in the order can always proceed.
 //
 // Each unknown is computed from one row of the factors, with the updates subtracted
 // one at a time in the order the column sweep applies them: the coupling entries of
@@ -22,6 +26,7 @@
 // does not depend on the schedule.
 #include "device.hpp"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -148,11 +153,465 @@ __device__ __forceinline__ bool row_update(double& acc, const RowPre& r, const u
   return !__any(stalled);
 }
 
-template <bool kLds>
-__device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, const Flags<kLds>& F, int kind, int id, int rhs,
-                         int tid) {
+// Rows in flight per wavefront: each wave loads the entries of its next kPre rows while
+// it works on the current one, so a row's global loads are issued kPre rows early.
+constexpr int kPre = 4;
+
+// One sweep of a task over its rows in issue order: row q of the order is taken by wave
+// q mod kSW.  `P` holds the rows' entry ranges by task-local row, `O` the issue order
+// (task-local rows, minus `ooff`), null for the plain order (ascending for L, descending
+// for U).  The backward sweep divides by the diagonal.  Returns false on a stall.
+template <bool kLds, bool kBack>
+__device__ __forceinline__ bool sweep(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O, int ooff,
+                                      const unsigned long long* keys, const double* vals, const Flags<kLds>& F,
+                                      const double* fin, int r0, int m, int wv, int lane) {
+  const int n = a.n;
+  RowPre pre[kPre];
+  int kr[kPre];
+  double dg[kPre];
+#pragma unroll
+  for (int i = 0; i < kPre; i++) {
+    const int q = wv + i * kSW;
+    kr[i] = 0;
+    dg[i] = 1.0;
+    if (q < m) {
+      kr[i] = O ? O[q] - ooff : (kBack ? m - 1 - q : q);
+      row_prefetch(pre[i], P, keys, vals, kr[i], kBack, n, lane);
+      if (kBack) dg[i] = a.diag[r0 + kr[i]];
+    }
+  }
+  bool ok = true;
+  for (int q0 = wv; q0 < m; q0 += kPre * kSW) {
+#pragma unroll
+    for (int i = 0; i < kPre; i++) {
+      const int q = q0 + i * kSW;
+      if (q < m) {
+        double acc = V[kr[i]];
+        ok &= row_update<kLds>(acc, pre[i], keys, vals, kBack, n, r0, m, V, F, fin, lane);
+        if (kBack) acc = acc / dg[i];
+        if (lane == 0) V[kr[i]] = acc;
+        publish_fence<kLds>();
+        if (lane == 0) F.set(kr[i]);
+        const int qn = q + kPre * kSW;
+        if (qn < m) {
+          kr[i] = O ? O[qn] - ooff : (kBack ? m - 1 - qn : qn);
+          row_prefetch(pre[i], P, keys, vals, kr[i], kBack, n, lane);
+          if (kBack) dg[i] = a.diag[r0 + kr[i]];
+        }
+      }
+    }
+  }
+  return ok;
+}
+
+// Entries a thread holds in LDS for its current row (the lane-per-row sweep).
+constexpr int kSlot = 8;
+
+// LDS slots of the lane-per-row sweep: kSlot entries for each of the 64 kSW threads,
+// entry t of thread i at t * 64 kSW + i: the task-local row of the entry's column (-1
+// for a column outside the task, whose product the prefix pass already subtracted) and
+// the entry's value.
+struct Slots {
+  int32_t* Sj;
+  double* Sx;
+};
+
+// A row's first kSlot entries in registers (loaded a round before their use).
+struct RowRegs {
+  int k, e0, e1;
+  double d;
+  double acc;
+  int j[kSlot];
+  double x[kSlot];
+};
+
+template <bool kBack>
+__device__ __forceinline__ void load_row_regs(RowRegs& R, const SolveArgs& a, const int32_t* P, const int32_t* O,
+                                              const unsigned long long* keys, const double* vals, const double* A0,
+                                              int r0, int m, int q) {
+  R.k = -1;
+  R.e0 = R.e1 = 0;
+  R.d = 1.0;
+  R.acc = 0.0;
+  if (q < m) {
+    R.k = O ? O[q] : (kBack ? m - 1 - q : q);
+    R.e0 = P[R.k];
+    R.e1 = P[R.k + 1];
+    R.acc = A0[R.k];
+    if (kBack) R.d = a.diag[r0 + R.k];
+  }
+#pragma unroll
+  for (int t = 0; t < kSlot; t++) {
+    R.j[t] = 0;
+    R.x[t] = 0.0;
+    if (R.e0 + t < R.e1) {
+      const unsigned lo = (unsigned)keys[R.e0 + t];
+      R.j[t] = kBack ? a.n - 1 - (int)lo : (int)lo;
+      R.x[t] = vals[R.e0 + t];
+    }
+  }
+}
+
+__device__ __forceinline__ void store_slots(const Slots& S, int tid, const int* j, const double* x, int from, int e1,
+                                            int r0, int m) {
+  constexpr int T = 64 * kSW;
+#pragma unroll
+  for (int t = 0; t < kSlot; t++) {
+    if (from + t < e1) {
+      const int jj = j[t] - r0;
+      S.Sj[t * T + tid] = (jj >= 0 && jj < m) ? jj : -1;
+      S.Sx[t * T + tid] = x[t];
+    }
+  }
+}
+
+// The prefix of a row: its entries in columns outside the task come first in the
+// sweep's order (columns of earlier tasks: descendants' before an ND node's own in L,
+// ancestors' before them in U), and their values are final.  Thread per row, four
+// entries' loads at a time; V[kk] -= the prefix, products subtracted one at a time.
+template <bool kBack>
+__device__ __forceinline__ void apply_prefixes(const SolveArgs& a, double* G, const int32_t* P,
+                                               const unsigned long long* keys, const double* vals, const double* fin,
+                                               int r0, int m, int tid) {
+  const int n = a.n;
+  for (int kk = tid; kk < m; kk += 64 * kSW) {
+    int e = P[kk];
+    const int e1 = P[kk + 1];
+    double acc = G[kk];
+    bool more = true;
+    while (more && e < e1) {
+      int j[4];
+      double x[4], f[4];
+      bool out[4];
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        j[t] = 0;
+        x[t] = 0.0;
+        if (e + t < e1) {
+          const unsigned lo = (unsigned)keys[e + t];
+          j[t] = kBack ? n - 1 - (int)lo : (int)lo;
+          x[t] = vals[e + t];
+        }
+        out[t] = e + t < e1 && (j[t] < r0 || j[t] >= r0 + m);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; t++) f[t] = out[t] ? fin[j[t]] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        if (more && out[t]) acc = acc - x[t] * f[t];
+        else more = false;
+      }
+      e += 4;
+    }
+    G[kk] = acc;
+  }
+}
+
+// In the lane-per-row sweep a row's LDS value is its done flag: V holds kPending until
+// the row's result is stored there with one 64-bit access.  kPending is a signaling NaN,
+// which no arithmetic result equals; a result with exactly that bit pattern (only a
+// copied input can have it) is stored quieted.
+constexpr unsigned long long kPending = 0x7ff0dead5a5a5a5aull;
+
+__device__ __forceinline__ bool pending_load(const double* V, int i, double& v) {
+  const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(V) + i, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+  v = __longlong_as_double((long long)b);
+  return b != kPending;
+}
+
+__device__ __forceinline__ void result_store(double* V, int i, double z) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(z);
+  if (b == kPending) b |= 1ull << 51;
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(V) + i, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The sweep with one row per thread, for tasks in LDS whose rows are short: 64 kSW rows
+// in flight.  The wavefronts work in rounds: in round r lane i of wave w takes position
+// r 64 kSW + 64 w + i of the issue order, and the wave moves to its next round once all
+// its rows are done.  A row's first entries are loaded into registers a round ahead and
+// put into LDS slots when its round begins, so inside a round only rows longer than
+// kSlot load from global memory.  A thread never blocks: every pass it subtracts the
+// next entry of its row if that entry's row is done, so lanes waiting on one another
+// still advance; entries are subtracted one at a time in the row's order.  Returns
+// false on a stall.
+template <bool kBack>
+__device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
+                                            const unsigned long long* keys, const double* vals, const double* A0,
+                                            const Slots& S, int r0, int m, int tid) {
+  constexpr int T = 64 * kSW;
+  const int n = a.n;
+  RowRegs nx;
+  load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, r0, m, tid);
+  unsigned idle = 0;
+  bool stalled = false;
+  for (int q = tid; __any(q < m); q += T) {
+    const int kc = nx.k;
+    int p = nx.e0, sb = nx.e0;
+    const int e1 = nx.e1;
+    const double dg = nx.d;
+    double acc = nx.acc;
+    bool busy = kc >= 0;
+    if (busy) store_slots(S, tid, nx.j, nx.x, p, e1, r0, m);
+    load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, r0, m, q + T);
+    while (__any(busy)) {
+      bool prog = false;
+      if (busy) {
+        if (p < e1) {
+          if (p - sb == kSlot) {
+            int j[kSlot];
+            double x[kSlot];
+#pragma unroll
+            for (int t = 0; t < kSlot; t++) {
+              j[t] = 0;
+              x[t] = 0.0;
+              if (p + t < e1) {
+                const unsigned lo = (unsigned)keys[p + t];
+                j[t] = kBack ? n - 1 - (int)lo : (int)lo;
+                x[t] = vals[p + t];
+              }
+            }
+            sb = p;
+            store_slots(S, tid, j, x, p, e1, r0, m);
+          }
+          // branch-free: up to four entries of the slots (indices clamped into the row
+          // and the slots) and their rows' values read together, then the leading
+          // ready ones subtracted
+          const int lim = (e1 - sb < kSlot ? e1 - sb : kSlot) - 1;
+          int jl[4];
+          double xs[4], v[4];
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            const int u = p - sb + t < lim ? p - sb + t : lim;
+            jl[t] = S.Sj[u * T + tid];
+            xs[t] = S.Sx[u * T + tid];
+          }
+          bool rdy[4];
+#pragma unroll
+          for (int t = 0; t < 4; t++) rdy[t] = pending_load(V, jl[t] >= 0 ? jl[t] : 0, v[t]) || jl[t] < 0;
+          bool go = true;
+          int c = 0;
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            go = go && rdy[t] && p - sb + t <= lim;
+            const double upd = acc - xs[t] * v[t];
+            acc = (go && jl[t] >= 0) ? upd : acc;
+            c += go ? 1 : 0;
+          }
+          p += c;
+          prog = c > 0;
+        }
+        if (p >= e1) {
+          result_store(V, kc, kBack ? acc / dg : acc);
+          busy = false;
+          prog = true;
+        }
+      }
+      if (__any(prog)) {
+        idle = 0;
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+        if (++idle > kSpinLimit) { stalled = true; break; }
+      }
+    }
+    if (stalled) break;
+  }
+  return !stalled;
+}
+
+// Residual of task row kk: the right-hand side minus the coupling to finished later
+// blocks, in the sweep's order; the entries' loads are issued four at a time.
+__device__ __forceinline__ double residual_row(const SolveArgs& a, const double* Bc, const double* Z, int i) {
+  double acc = Bc[a.prow[i]];
+  int q = a.OTp[i];
+  const int qe = a.OTp[i + 1];
+  for (; q + 4 <= qe; q += 4) {
+    const int j0 = a.OTj[q], j1 = a.OTj[q + 1], j2 = a.OTj[q + 2], j3 = a.OTj[q + 3];
+    const double x0 = a.OTx[q], x1 = a.OTx[q + 1], x2 = a.OTx[q + 2], x3 = a.OTx[q + 3];
+    const double z0 = Z[j0], z1 = Z[j1], z2 = Z[j2], z3 = Z[j3];
+    acc = acc - x0 * z0;
+    acc = acc - x1 * z1;
+    acc = acc - x2 * z2;
+    acc = acc - x3 * z3;
+  }
+  if (q < qe) {
+    const int c = qe - q;
+    const int j0 = a.OTj[q], j1 = c > 1 ? a.OTj[q + 1] : 0, j2 = c > 2 ? a.OTj[q + 2] : 0;
+    const double x0 = a.OTx[q], x1 = c > 1 ? a.OTx[q + 1] : 0.0, x2 = c > 2 ? a.OTx[q + 2] : 0.0;
+    const double z0 = Z[j0], z1 = c > 1 ? Z[j1] : 0.0, z2 = c > 2 ? Z[j2] : 0.0;
+    acc = acc - x0 * z0;
+    if (c > 1) acc = acc - x1 * z1;
+    if (c > 2) acc = acc - x2 * z2;
+  }
+  return acc;
+}
+
+// The sweep with one row per thread on a task whose entries are all in LDS: Ej holds the
+// task-local row of every entry's column (-1 outside the task), Ex its value, entry e of
+// the rows at e - e_base.  Rounds and the never-blocking loop as in sweep_lanes; a pass
+// reads up to four entries of the row and their rows' values together and subtracts the
+// leading ones whose rows are done.  Returns false on a stall.
+template <bool kBack>
+__device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
+                                             const int32_t* Ej, const double* Ex, int e_base, const double* A0,
+                                             int r0, int m, int tid) {
+  constexpr int T = 64 * kSW;
+  // the next round's row, a round ahead: task-local row, entry range, initial value, diagonal
+  int nk = -1, ne0 = 0, ne1 = 0;
+  double nacc = 0.0, nd = 1.0;
+  auto fetch = [&](int q) {
+    nk = -1;
+    if (q < m) {
+      nk = O ? O[q] : (kBack ? m - 1 - q : q);
+      ne0 = P[nk] - e_base;
+      ne1 = P[nk + 1] - e_base;
+      nacc = A0[nk];
+      if (kBack) nd = a.diag[r0 + nk];
+    }
+  };
+  fetch(tid);
+  unsigned idle = 0;
+  bool stalled = false;
+  for (int q = tid; __any(q < m); q += T) {
+    const int kc = nk, e1 = ne1;
+    int p = ne0;
+    double acc = nacc;
+    const double dg = nd;
+    bool busy = kc >= 0;
+    fetch(q + T);
+    while (__any(busy)) {
+      bool prog = false;
+      if (busy) {
+        if (p < e1) {
+          // branch-free: the four entries (indices clamped into the row) and their
+          // rows' values are read together, then the leading ready ones subtracted
+          int j[4];
+          double x[4], v[4];
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            const int e = p + t < e1 ? p + t : e1 - 1;
+            j[t] = Ej[e];
+            x[t] = Ex[e];
+          }
+          bool rdy[4];
+#pragma unroll
+          for (int t = 0; t < 4; t++) rdy[t] = pending_load(V, j[t] >= 0 ? j[t] : 0, v[t]) || j[t] < 0;
+          bool go = true;
+          int c = 0;
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            go = go && rdy[t] && p + t < e1;
+            const double upd = acc - x[t] * v[t];
+            acc = (go && j[t] >= 0) ? upd : acc;
+            c += go ? 1 : 0;
+          }
+          p += c;
+          prog = c > 0;
+        }
+        if (p >= e1) {
+          result_store(V, kc, kBack ? acc / dg : acc);
+          busy = false;
+          prog = true;
+        }
+      }
+      if (__any(prog)) {
+        idle = 0;
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+        if (++idle > kSpinLimit) { stalled = true; break; }
+      }
+    }
+    if (stalled) break;
+  }
+  return !stalled;
+}
+
+// Copy the task's entries [e_base, e_base + E) into LDS: columns as task-local rows (-1
+// outside the task), eight loads in flight per thread.
+template <bool kBack>
+__device__ __forceinline__ void stage_entries(int32_t* Ej, double* Ex, const unsigned long long* keys,
+                                              const double* vals, int e_base, int E, int r0, int m, int n, int tid) {
+  constexpr int T = 64 * kSW;
+  for (int e = tid; e < E; e += 8 * T) {
+    unsigned lo[8];
+    double x[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      lo[t] = 0u;
+      x[t] = 0.0;
+      if (e + t * T < E) {
+        lo[t] = (unsigned)keys[e_base + e + t * T];
+        x[t] = vals[e_base + e + t * T];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      if (e + t * T < E) {
+        const int jj = (kBack ? n - 1 - (int)lo[t] : (int)lo[t]) - r0;
+        Ej[e + t * T] = (jj >= 0 && jj < m) ? jj : -1;
+        Ex[e + t * T] = x[t];
+      }
+    }
+  }
+}
+
+// A task in LDS whose rows hold at most this many entries on average runs its sweeps
+// one row per thread; longer rows (ND separators) one row per wavefront.
+constexpr int kLaneMeanMax = 24;
+
+// LDS of a task: V (m doubles), row pointers (m + 1), issue order (m), then a region R
+// of rbytes for the sweep: the done bits (row per wavefront), the entries (row per
+// thread, all entries in LDS) or the entry slots (row per thread, kSlot entries each).
+__host__ __device__ constexpr int64_t lds_base_bytes(int64_t m) { return (8 * m + 4 * (2 * m + 1) + 7) / 8 * 8; }
+__host__ __device__ constexpr int64_t lds_flag_bytes(int64_t m) { return 4 * ((m + 31) / 32 + 1); }
+__host__ __device__ constexpr int64_t lds_slot_bytes() { return 12 * (int64_t)kSlot * 64 * kSW; }
+
+// One sweep (L forward, or U backward) of a task over its rows.  V holds the initial
+// values and receives the results.  P / O: the row pointers and issue order (LDS for a
+// task in LDS, else global with O offset by r0); `fin` the final values of columns
+// outside the task.
+template <bool kLds, bool kBack>
+__device__ __forceinline__ bool run_sweep(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O, int ooff,
+                                          char* R, int64_t rbytes, const Flags<kLds>& F, const unsigned long long* keys,
+                                          const double* vals, const double* fin, double* G, bool prefix, int r0, int m,
+                                          int tid) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
+  if constexpr (kLds) {
+    const int e_base = P[0];
+    const int E = P[m] - e_base;
+    if (E <= kLaneMeanMax * m && (12 * (int64_t)E <= rbytes || lds_slot_bytes() <= rbytes)) {
+      // one row per thread: initial values to G (the task's rows of W, free until the
+      // task's results), LDS values to pending
+      for (int kk = tid; kk < m; kk += 64 * kSW) {
+        G[kk] = V[kk];
+        V[kk] = __longlong_as_double((long long)kPending);
+      }
+      __syncthreads();
+      if (prefix) {
+        apply_prefixes<kBack>(a, G, P, keys, vals, fin, r0, m, tid);
+        __syncthreads();
+      }
+      if (12 * (int64_t)E <= rbytes) {
+        double* Ex = reinterpret_cast<double*>(R);
+        int32_t* Ej = reinterpret_cast<int32_t*>(Ex + E);
+        stage_entries<kBack>(Ej, Ex, keys, vals, e_base, E, r0, m, a.n, tid);
+        __syncthreads();
+        return sweep_staged<kBack>(a, V, P, O, Ej, Ex, e_base, G, r0, m, tid);
+      }
+      double* Sx = reinterpret_cast<double*>(R);
+      int32_t* Sj = reinterpret_cast<int32_t*>(Sx + kSlot * 64 * kSW);
+      return sweep_lanes<kBack>(a, V, P, O, keys, vals, G, Slots{Sj, Sx}, r0, m, tid);
+    }
+  }
+  return sweep<kLds, kBack>(a, V, P, O, ooff, keys, vals, F, fin, r0, m, wv, lane);
+}
+
+// Pl: LDS row pointers (m + 1), Po: LDS issue order (m), R: the LDS region of the
+// sweeps, when the task is in LDS
+template <bool kLds>
+__device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po, char* R, int64_t rbytes,
+                         const Flags<kLds>& F, int kind, int id, int rhs, int tid) {
   int r0, r1;
   if (kind == 0) { r0 = a.blkptr[id]; r1 = a.blkptr[id + 1]; }
   else { r0 = a.grpptr[id]; r1 = a.grpptr[id + 1]; }
@@ -161,39 +620,28 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, const Flags
   double* W = a.W + (int64_t)rhs * n;
   double* Z = a.Z + (int64_t)rhs * n;
   const double* Bc = a.B + (int64_t)rhs * a.ldb;
+  const int obad = a.obad[r0];
   bool ok = true;
   if (kind != 2) {
-    // residual of every row (independent of the task's other rows): the right-hand
-    // side minus the coupling to finished later blocks, in the sweep's order
+    // residual of every row (independent of the task's other rows)
     F.clear(m, tid);
-    for (int kk = tid; kk < m; kk += 64 * kSW) {
-      const int i = a.piv[r0 + kk];
-      double acc = Bc[a.prow[i]];
-      for (int q = a.OTp[i]; q < a.OTp[i + 1]; q++) {
-        const double prod = a.OTx[q] * Z[a.OTj[q]];
-        acc = acc - prod;
-      }
-      V[kk] = acc;
-    }
-    // the task's L row pointers
+    for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = residual_row(a, Bc, Z, a.piv[r0 + kk]);
+    // the task's L row pointers and forward order
     const int32_t* LP = a.LTp + r0;
+    const int32_t* ord = (obad & 1) == 0 ? a.sfo + r0 : nullptr;
+    int ooff = r0;
     if (kLds) {
       for (int kk = tid; kk <= m; kk += 64 * kSW) Pl[kk] = a.LTp[r0 + kk];
       LP = Pl;
+      if (ord) {
+        for (int kk = tid; kk < m; kk += 64 * kSW) Po[kk] = ord[kk] - r0;
+        ord = Po;
+        ooff = 0;
+      }
     }
     __syncthreads();
-    // L rows, ascending
-    RowPre cur, nxt;
-    if (wv < m) row_prefetch(cur, LP, a.lkeys, a.lvals, wv, false, n, lane);
-    for (int kk = wv; kk < m; kk += kSW) {
-      if (kk + kSW < m) row_prefetch(nxt, LP, a.lkeys, a.lvals, kk + kSW, false, n, lane);
-      double acc = V[kk];
-      ok &= row_update<kLds>(acc, cur, a.lkeys, a.lvals, false, n, r0, m, V, F, W, lane);
-      if (lane == 0) V[kk] = acc;
-      publish_fence<kLds>();
-      if (lane == 0) F.set(kk);
-      cur = nxt;
-    }
+    ok &= run_sweep<kLds, false>(a, V, LP, ord, ooff, R, rbytes, F, a.lkeys, a.lvals, W, W + r0, kind == 1, r0, m,
+                                 tid);
     __syncthreads();
     if (kind == 1) {
       for (int kk = tid; kk < m; kk += 64 * kSW) W[r0 + kk] = V[kk];
@@ -203,38 +651,23 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, const Flags
   } else {
     for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = W[r0 + kk];
   }
-  // U rows, descending: z_k = (w_k - sum_{j > k} u_kj z_j) / u_kk
+  // U rows: z_k = (w_k - sum_{j > k} u_kj z_j) / u_kk
   F.clear(m, tid);
   __syncthreads();
   const int32_t* UP = a.UTp + r0;
+  const int32_t* ord = (obad & 2) == 0 ? a.sbo + r0 : nullptr;
+  int ooff = r0;
   if (kLds) {
     for (int kk = tid; kk <= m; kk += 64 * kSW) Pl[kk] = a.UTp[r0 + kk];
     UP = Pl;
+    if (ord) {
+      for (int kk = tid; kk < m; kk += 64 * kSW) Po[kk] = ord[kk] - r0;
+      ord = Po;
+      ooff = 0;
+    }
   }
   __syncthreads();
-  {
-    RowPre cur, nxt;
-    double dcur = 1.0, dnxt = 1.0;
-    if (wv < m) {
-      row_prefetch(cur, UP, a.ukeys, a.uvals, m - 1 - wv, true, n, lane);
-      dcur = a.diag[r1 - 1 - wv];
-    }
-    for (int q = wv; q < m; q += kSW) {
-      const int kk = m - 1 - q;
-      if (q + kSW < m) {
-        row_prefetch(nxt, UP, a.ukeys, a.uvals, kk - kSW, true, n, lane);
-        dnxt = a.diag[r0 + kk - kSW];
-      }
-      double acc = V[kk];
-      ok &= row_update<kLds>(acc, cur, a.ukeys, a.uvals, true, n, r0, m, V, F, Z, lane);
-      const double z = acc / dcur;
-      if (lane == 0) V[kk] = z;
-      publish_fence<kLds>();
-      if (lane == 0) F.set(kk);
-      cur = nxt;
-      dcur = dnxt;
-    }
-  }
+  ok &= run_sweep<kLds, true>(a, V, UP, ord, ooff, R, rbytes, F, a.ukeys, a.uvals, Z, W + r0, kind == 2, r0, m, tid);
   __syncthreads();
   for (int kk = tid; kk < m; kk += 64 * kSW) Z[r0 + kk] = V[kk];
   if (!ok && tid == 0) atomicOr(a.status, 4);
@@ -246,19 +679,21 @@ __global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
   const int t = a.t_begin + (int)blockIdx.x;
   const int kind = a.st_kind[t], id = a.st_id[t];
   const int m = kind == 0 ? a.blkptr[id + 1] - a.blkptr[id] : a.grpptr[id + 1] - a.grpptr[id];
-  const bool lds = m <= a.lds_doubles;
+  const int64_t rbytes = (int64_t)a.lds_bytes - lds_base_bytes(m);
+  const bool lds = rbytes >= lds_flag_bytes(m);
   for (int rhs = 0; rhs < a.nrhs; rhs++) {
     if (lds) {
-      // LDS: work vector (lds_doubles), row pointers (lds_doubles + 1), done bits
-      int32_t* Pl = reinterpret_cast<int32_t*>(smem_d + a.lds_doubles);
-      Flags<true> F{reinterpret_cast<unsigned*>(Pl + a.lds_doubles + 1), nullptr};
-      run_task<true>(a, smem_d, Pl, F, kind, id, rhs, tid);
+      int32_t* Pl = reinterpret_cast<int32_t*>(smem_d + m);
+      int32_t* Po = Pl + m + 1;
+      char* R = reinterpret_cast<char*>(smem_d) + lds_base_bytes(m);
+      Flags<true> F{reinterpret_cast<unsigned*>(R), nullptr};
+      run_task<true>(a, smem_d, Pl, Po, R, rbytes, F, kind, id, rhs, tid);
     } else {
       const int r0 = kind == 0 ? a.blkptr[id] : a.grpptr[id];
       Flags<false> F{nullptr, a.sflag + r0};
       // work vector in place: the block's (or node's) part of Z, or of W for a forward task
       double* V = (kind == 1 ? a.W : a.Z) + (int64_t)rhs * a.n + r0;
-      run_task<false>(a, V, nullptr, F, kind, id, rhs, tid);
+      run_task<false>(a, V, nullptr, nullptr, nullptr, 0, F, kind, id, rhs, tid);
     }
     __syncthreads();
   }
@@ -276,9 +711,8 @@ __global__ void solve_unpermute_kernel(SolveArgs a) {
 
 }  // namespace
 
-size_t solve_lds_bytes(int32_t work_doubles) {
-  return sizeof(double) * (size_t)work_doubles + sizeof(int32_t) * ((size_t)work_doubles + 1) +
-         sizeof(unsigned) * (((size_t)work_doubles + 31) / 32 + 1);
+size_t solve_lds_bytes(int32_t rows) {
+  return (size_t)(lds_base_bytes(rows) + std::max(lds_flag_bytes(rows), lds_slot_bytes()));
 }
 
 hipError_t solve_lds_setup(size_t max_bytes) {
@@ -288,7 +722,7 @@ hipError_t solve_lds_setup(size_t max_bytes) {
 
 hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s) {
   if (ntasks > 0)
-    hipLaunchKernelGGL(solve_task_kernel, dim3(ntasks), dim3(64 * kSW), solve_lds_bytes(a.lds_doubles), s, a);
+    hipLaunchKernelGGL(solve_task_kernel, dim3(ntasks), dim3(64 * kSW), (size_t)a.lds_bytes, s, a);
   return hipGetLastError();
 }
 

@@ -1320,7 +1320,12 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
   P.co_max_item_cols = 0;
   P.sym_ok = false;
   P.sym_lnz = P.sym_unz = P.sym_cb = 0;
-  if (nlev < 1 || n == 0) { P.sym_ok = true; return; }
+  if (nlev < 1 || n == 0) {
+    P.sym_ok = true;
+    P.sfo.clear();
+    build_solve_orders(P, nullptr, false);
+    return;
+  }
   // segment of every column, level of every segment
   std::vector<int32_t> col_seg(n, -1);
   for (size_t sg = 0; sg < P.seg_c0.size(); sg++)
@@ -1452,6 +1457,54 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
   }
   P.sym_ok = within;
   build_issue_order(P);
+  if (deps_ok) {
+    std::vector<std::vector<int32_t>> lr(n);
+    for (int k = 0; k < n; k++)
+      if (P.col_item[k] >= 0) lr[k].assign(Lrows.begin() + Lb[k], Lrows.begin() + Le[k]);
+    build_solve_orders(P, &lr, true);
+  } else {
+    P.sfo.clear();
+    build_solve_orders(P, nullptr, false);
+  }
+}
+
+void build_solve_orders(Plan& P, const std::vector<std::vector<int32_t>>* lrows, bool backward) {
+  const int n = P.n;
+  const bool fresh = (int)P.sfo.size() != n;
+  P.sfo.resize(n); P.sbo.resize(n); P.sfo_pos.resize(n); P.sbo_pos.resize(n);
+  P.row_task0.assign(n, 0);
+  std::vector<char> seen(n + 1, 0);
+  std::vector<int32_t> fl(n, 0), bl(n, 0), ord;
+  for (size_t q = 0; q < P.st_kind.size(); q++) {
+    const int kind = P.st_kind[q], id = P.st_id[q];
+    const int r0 = kind == 0 ? P.blkptr[id] : P.grpptr[id];
+    const int r1 = kind == 0 ? P.blkptr[id + 1] : P.grpptr[id + 1];
+    const int m = r1 - r0;
+    if (m <= 0 || seen[r0]) continue;   // an ND node's forward and backward tasks share rows
+    seen[r0] = 1;
+    for (int k = r0; k < r1; k++) P.row_task0[k] = r0;
+    // predictions exist for the first-level segments only; separators keep plain order
+    const bool l0 = !P.col_item.empty() && P.col_item[r0] >= 0;
+    ord.resize(m);
+    if (lrows || fresh) {
+      if (l0 && lrows)
+        for (int j = r0; j < r1; j++)
+          for (int r : (*lrows)[j])
+            if (r < r1) fl[r] = std::max(fl[r], fl[j] + 1);
+      std::iota(ord.begin(), ord.end(), r0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return fl[x] < fl[y]; });
+      for (int i = 0; i < m; i++) { P.sfo[r0 + i] = ord[i]; P.sfo_pos[ord[i]] = i; }
+    }
+    if (l0 && backward)
+      for (int j = r1 - 1; j >= r0; j--)
+        for (int32_t e = P.dep_ptr[j]; e < P.dep_ptr[j + 1]; e++) {
+          const int k = P.dep_idx[e];
+          if (k >= r0 && k < j) bl[k] = std::max(bl[k], bl[j] + 1);
+        }
+    for (int i = 0; i < m; i++) ord[i] = r1 - 1 - i;   // plain backward order: descending
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bl[x] < bl[y]; });
+    for (int i = 0; i < m; i++) { P.sbo[r0 + i] = ord[i]; P.sbo_pos[ord[i]] = i; }
+  }
 }
 
 void build_issue_order(Plan& P) {
@@ -1519,6 +1572,7 @@ int64_t merge_learned_deps(Plan& P, const std::vector<int32_t>& items, const std
   P.dep_ptr = std::move(ptr);
   P.dep_idx = std::move(idx);
   build_issue_order(P);
+  build_solve_orders(P, nullptr, true);
   return added;
 }
 

@@ -96,6 +96,15 @@ struct Plan {
   // graph, so the columns a workgroup's waves take next are independent of each other
   std::vector<int32_t> co_item_off, co_issue;
   bool co_valid = false;                      // set by the library after checking the lists
+  // Solve issue orders: the rows of every solve task (a block without ND, or an ND
+  // node) in the order its wavefronts take them, rows of one level of the task's
+  // dependency graph together -- the L sweep by levels of the predicted L pattern, the U
+  // sweep by levels of the predicted U pattern (the dependency lists) -- or plain
+  // order (ascending for L, descending for U) where no prediction exists.  row_task0 is
+  // the first row of the task holding each row; *_pos the rank of a row in its task's
+  // order.  The device checks the orders against the actual patterns after every
+  // factorization.
+  std::vector<int32_t> sfo, sbo, sfo_pos, sbo_pos, row_task0;
   // fill of a factorization without row exchanges, from the host symbolic pass (sizes
   // the L/U pools and the separator buffer); sym_ok false when the pass was cut short
   bool sym_ok = false;
@@ -127,6 +136,11 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget);
 
 // Issue order of every item from the predicted lists (after they change).
 void build_issue_order(Plan& P);
+
+// Solve issue orders: forward from the predicted L rows `lrows` of the first-level
+// columns (null: keep the current forward orders, or plain ones on the first call),
+// backward from the dependency lists (or plain when `backward` is false).
+void build_solve_orders(Plan& P, const std::vector<std::vector<int32_t>>* lrows, bool backward);
 
 // Merge the dependencies observed in a factorization (U pattern of every level-0 column
 // of the given items) into the predicted lists: returns entries added.
