@@ -352,53 +352,61 @@ __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const
     const double dg = nx.d;
     double acc = nx.acc;
     bool busy = kc >= 0;
-    if (busy) store_slots(S, tid, nx.j, nx.x, p, e1, r0, m);
+    // the window: entries p and p + 1 of the row, the second only while it is in the
+    // slots (lim: the last slot holding an entry)
+    int j0 = -1, j1 = -1, lim = 0;
+    double x0 = 0.0, x1 = 0.0;
+    if (busy) {
+      store_slots(S, tid, nx.j, nx.x, p, e1, r0, m);
+      if (p < e1) {
+        lim = (e1 - sb < kSlot ? e1 - sb : kSlot) - 1;
+        j0 = nx.j[0] - r0;
+        j0 = (j0 >= 0 && j0 < m) ? j0 : -1;
+        x0 = nx.x[0];
+        j1 = nx.j[1] - r0;
+        j1 = (j1 >= 0 && j1 < m) ? j1 : -1;
+        x1 = nx.x[1];
+      }
+    }
     load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, r0, m, q + T);
     while (__any(busy)) {
       bool prog = false;
       if (busy) {
         if (p < e1) {
-          if (p - sb == kSlot) {
-            int j[kSlot];
-            double x[kSlot];
-#pragma unroll
-            for (int t = 0; t < kSlot; t++) {
-              j[t] = 0;
-              x[t] = 0.0;
-              if (p + t < e1) {
-                const unsigned lo = (unsigned)keys[p + t];
-                j[t] = kBack ? n - 1 - (int)lo : (int)lo;
-                x[t] = vals[p + t];
-              }
-            }
-            sb = p;
-            store_slots(S, tid, j, x, p, e1, r0, m);
-          }
-          // branch-free: up to four entries of the slots (indices clamped into the row
-          // and the slots) and their rows' values read together, then the leading
-          // ready ones subtracted
-          const int lim = (e1 - sb < kSlot ? e1 - sb : kSlot) - 1;
-          int jl[4];
-          double xs[4], v[4];
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            const int u = p - sb + t < lim ? p - sb + t : lim;
-            jl[t] = S.Sj[u * T + tid];
-            xs[t] = S.Sx[u * T + tid];
-          }
-          bool rdy[4];
-#pragma unroll
-          for (int t = 0; t < 4; t++) rdy[t] = pending_load(V, jl[t] >= 0 ? jl[t] : 0, v[t]) || jl[t] < 0;
-          bool go = true;
-          int c = 0;
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            go = go && rdy[t] && p - sb + t <= lim;
-            const double upd = acc - xs[t] * v[t];
-            acc = (go && jl[t] >= 0) ? upd : acc;
-            c += go ? 1 : 0;
-          }
+          double v0 = 0.0, v1 = 0.0;
+          const bool c0 = pending_load(V, j0 >= 0 ? j0 : 0, v0) || j0 < 0;
+          const bool c1 = c0 && (pending_load(V, j1 >= 0 ? j1 : 0, v1) || j1 < 0) && p - sb + 1 <= lim;
+          double u = acc - x0 * v0;
+          acc = (c0 && j0 >= 0) ? u : acc;
+          u = acc - x1 * v1;
+          acc = (c1 && j1 >= 0) ? u : acc;
+          const int c = (int)c0 + (int)c1;
           p += c;
+          if (c > 0 && p < e1) {
+            if (p - sb >= kSlot) {
+              // past the slots: the next kSlot entries from global memory
+              int j[kSlot];
+              double x[kSlot];
+#pragma unroll
+              for (int t = 0; t < kSlot; t++) {
+                j[t] = 0;
+                x[t] = 0.0;
+                if (p + t < e1) {
+                  const unsigned lo = (unsigned)keys[p + t];
+                  j[t] = kBack ? n - 1 - (int)lo : (int)lo;
+                  x[t] = vals[p + t];
+                }
+              }
+              sb = p;
+              lim = (e1 - sb < kSlot ? e1 - sb : kSlot) - 1;
+              store_slots(S, tid, j, x, p, e1, r0, m);
+            }
+            const int u0 = p - sb, u1 = p - sb + 1 <= lim ? p - sb + 1 : lim;
+            j0 = S.Sj[u0 * T + tid];
+            x0 = S.Sx[u0 * T + tid];
+            j1 = S.Sj[u1 * T + tid];
+            x1 = S.Sx[u1 * T + tid];
+          }
           prog = c > 0;
         }
         if (p >= e1) {
@@ -448,9 +456,10 @@ __device__ __forceinline__ double residual_row(const SolveArgs& a, const double*
 
 // The sweep with one row per thread on a task whose entries are all in LDS: Ej holds the
 // task-local row of every entry's column (-1 outside the task), Ex its value, entry e of
-// the rows at e - e_base.  Rounds and the never-blocking loop as in sweep_lanes; a pass
-// reads up to four entries of the row and their rows' values together and subtracts the
-// leading ones whose rows are done.  Returns false on a stall.
+// the rows at e - e_base.  Rounds and the never-blocking loop as in sweep_lanes; a
+// thread keeps the next four entries of its row in registers, and a pass polls the
+// first two and subtracts the leading ones whose rows are done (one LDS round trip a
+// pass).  Returns false on a stall.
 template <bool kBack>
 __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
                                              const int32_t* Ej, const double* Ex, int e_base, const double* A0,
@@ -478,36 +487,53 @@ __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, cons
     double acc = nacc;
     const double dg = nd;
     bool busy = kc >= 0;
+    // the window: entries p .. p + 3 of the row (indices clamped into the row), in one
+    // of two register sets.  A pass polls the rows of the first two, and the moved
+    // window takes its first two entries from the old one and reads the other two into
+    // the other set: those reads complete while the next pass's polls are in flight.
+    struct Win {
+      int j0, j1, j2, j3;
+      double x0, x1, x2, x3;
+    };
+    auto at = [&](int e) { return e < e1 ? e : (e1 > 0 ? e1 - 1 : 0); };
+    Win wa{-1, -1, -1, -1, 0.0, 0.0, 0.0, 0.0}, wb = wa;
+    if (busy) {
+      wa.j0 = Ej[at(p)];
+      wa.x0 = Ex[at(p)];
+      wa.j1 = Ej[at(p + 1)];
+      wa.x1 = Ex[at(p + 1)];
+      wa.j2 = Ej[at(p + 2)];
+      wa.x2 = Ex[at(p + 2)];
+      wa.j3 = Ej[at(p + 3)];
+      wa.x3 = Ex[at(p + 3)];
+    }
     fetch(q + T);
-    while (__any(busy)) {
+    auto pass = [&](const Win& cur, Win& nxt) {
       bool prog = false;
       if (busy) {
-        if (p < e1) {
-          // branch-free: the four entries (indices clamped into the row) and their
-          // rows' values are read together, then the leading ready ones subtracted
-          int j[4];
-          double x[4], v[4];
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            const int e = p + t < e1 ? p + t : e1 - 1;
-            j[t] = Ej[e];
-            x[t] = Ex[e];
-          }
-          bool rdy[4];
-#pragma unroll
-          for (int t = 0; t < 4; t++) rdy[t] = pending_load(V, j[t] >= 0 ? j[t] : 0, v[t]) || j[t] < 0;
-          bool go = true;
-          int c = 0;
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            go = go && rdy[t] && p + t < e1;
-            const double upd = acc - x[t] * v[t];
-            acc = (go && j[t] >= 0) ? upd : acc;
-            c += go ? 1 : 0;
-          }
-          p += c;
-          prog = c > 0;
-        }
+        double v0 = 0.0, v1 = 0.0;
+        const bool r0_ = pending_load(V, cur.j0 >= 0 ? cur.j0 : 0, v0) || cur.j0 < 0;
+        const bool r1_ = pending_load(V, cur.j1 >= 0 ? cur.j1 : 0, v1) || cur.j1 < 0;
+        const bool c0 = p < e1 && r0_;
+        const bool c1 = c0 && p + 1 < e1 && r1_;
+        double u = acc - cur.x0 * v0;
+        acc = (c0 && cur.j0 >= 0) ? u : acc;
+        u = acc - cur.x1 * v1;
+        acc = (c1 && cur.j1 >= 0) ? u : acc;
+        const int c = (int)c0 + (int)c1;
+        p += c;
+        nxt.j0 = c == 0 ? cur.j0 : (c == 1 ? cur.j1 : cur.j2);
+        nxt.x0 = c == 0 ? cur.x0 : (c == 1 ? cur.x1 : cur.x2);
+        nxt.j1 = c == 0 ? cur.j1 : (c == 1 ? cur.j2 : cur.j3);
+        nxt.x1 = c == 0 ? cur.x1 : (c == 1 ? cur.x2 : cur.x3);
+        // materialise the moved entries here, while the reads below are in flight (an
+        // empty statement that only takes them as inputs)
+        asm volatile("" ::"v"(nxt.j0), "v"(nxt.j1), "v"(nxt.x0), "v"(nxt.x1));
+        nxt.j2 = Ej[at(p + 2)];
+        nxt.x2 = Ex[at(p + 2)];
+        nxt.j3 = Ej[at(p + 3)];
+        nxt.x3 = Ex[at(p + 3)];
+        prog = c > 0;
         if (p >= e1) {
           result_store(V, kc, kBack ? acc / dg : acc);
           busy = false;
@@ -518,8 +544,13 @@ __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, cons
         idle = 0;
       } else {
         __builtin_amdgcn_s_sleep(1);
-        if (++idle > kSpinLimit) { stalled = true; break; }
+        if (++idle > kSpinLimit) stalled = true;
       }
+    };
+    while (__any(busy) && !stalled) {
+      pass(wa, wb);
+      if (!__any(busy) || stalled) break;
+      pass(wb, wa);
     }
     if (stalled) break;
   }
