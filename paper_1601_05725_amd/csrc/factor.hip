@@ -100,6 +100,9 @@ struct Ws {
   double* st_val;
   int32_t* st_pre;
   int32_t* st_beg;
+  // stage offset of every pivotal list entry's L column when the reach staged it (LDS
+  // workspaces only; null: no staging during the reach)
+  int32_t* pso;
   int H;
   int NP;         // capacity of the pivotal list
   int shift;      // 32 - log2(H)
@@ -135,6 +138,7 @@ struct LdsWs {
   int32_t st_slot[SC];
   int32_t st_pre[72];
   int32_t st_beg[64];
+  int32_t pso[NP];
   int32_t cnt[4];
 };
 
@@ -248,7 +252,10 @@ __device__ void plist_sort(const Ws& w, int np) {
 // Expand the frontier entries [f0, f1) of the pivotal list: record each entry's
 // L column and insert its rows.  New pivotal rows join the list (next frontier).
 // plim: rows whose pivot column is >= plim count as not pivotal (see factor_column)
-__device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1, int plim) {
+// sfill: entries staged so far (-1: staging abandoned); returns the new value.  While
+// every expanded column fits in the stage, its L entries (workspace slot and value) are
+// staged on the way, with the entry's stage offset in pso, for the update.
+__device__ int expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1, int plim, int sfill) {
   const int lane = lane_id();
   for (int c0 = f0; c0 < f1; c0 += 64) {
     const int nb = uniform(f1 - c0 < 64 ? f1 - c0 : 64);
@@ -263,6 +270,9 @@ __device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1
     }
     const int excl = excl_scan(cnt, nb);
     const int total = rl(excl, nb - 1) + rl(cnt, nb - 1);
+    if (sfill >= 0 && sfill + total > w.SC) sfill = -1;
+    const bool stage = sfill >= 0;
+    if (stage && lane < nb) w.pso[e] = sfill + excl;
     if (nb > 8) {
       if (lane < nb) {
         w.st_pre[lane] = excl;
@@ -291,6 +301,8 @@ __device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1
       }
       if (t < total) {
         const int32_t r = a.Li[ob + (t - oe)];
+        double lx = 0.0;
+        if (stage) lx = a.Lx[ob + (t - oe)];
         bool isnew;
         int slot = ws_insert(w, r, &isnew);
         if (slot >= 0 && isnew) {
@@ -300,10 +312,16 @@ __device__ void expand_frontier(const FactorArgs& a, const Ws& w, int f0, int f1
           w.pv[slot] = pvr;
           if (pvr >= 0) plist_push(w, pvr, slot);
         }
+        if (stage) {
+          w.st_slot[sfill + t] = slot;
+          w.st_val[sfill + t] = lx;
+        }
       }
     }
+    if (stage) sfill += total;
   }
   wsync();
+  return sfill;
 }
 
 // Factor (or refactor) column k with workspace w.  Returns 0 on success, 1 when the
@@ -365,6 +383,8 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
   }
 
   int ub = 0, uc = 0, lb = 0, lc = 0, p = -1;
+  // staging of the reach's L columns for the update (LDS workspaces, full factorization)
+  int sfill = (w.pso != nullptr && !a.refactor) ? 0 : -1;
   if (!a.refactor || a.mode == 1) {
     if (use_pre) {
       // struct(R(:,k)) with values, loaded during the previous column
@@ -415,7 +435,7 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
     int f1 = w.cnt[1];
     while (f0 < f1) {
       if (w.cnt[2]) break;
-      expand_frontier(a, w, f0, f1, plim);
+      sfill = expand_frontier(a, w, f0, f1, plim, sfill);
       f0 = f1;
       f1 = w.cnt[1];
     }
@@ -490,10 +510,26 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
     if (__any(miss)) return 3;
   }
 
-  // sparse triangular update, ascending pivot order.  The L(:,j) entries of up to 64
-  // list entries at a time are gathered into LDS in one wave-wide pass, their rows
-  // resolved to workspace slots on the way, then applied column by column from LDS.
-  for (int e0 = 0; e0 < np; e0 += 64) {
+  // sparse triangular update, ascending pivot order.  When the reach staged every L
+  // column it expanded, the update runs from the stage.  Otherwise the L(:,j) entries of
+  // up to 64 list entries at a time are gathered into LDS in one wave-wide pass, their
+  // rows resolved to workspace slots on the way, then applied column by column from LDS.
+  const bool staged = sfill >= 0 && (!a.refactor || a.mode == 1);
+  if (staged) {
+    for (int t = 0; t < np; t++) {
+      const int src = (int)(w.sk[t] & 0xffffffffu);
+      const int o = w.pso[src], cj = w.pc[src];
+      const double xj = w.val[w.ps[src]];
+      for (int e = lane; e < cj; e += 64) {
+        const int slot = w.st_slot[o + e];
+        const double prod = w.st_val[o + e] * xj;
+        if (slot >= 0) w.val[slot] = w.val[slot] - prod;
+        else w.cnt[3] = 1;
+      }
+      wsync();
+    }
+  }
+  for (int e0 = 0; e0 < (staged ? 0 : np); e0 += 64) {
     const int nb = uniform(np - e0 < 64 ? np - e0 : 64);
     int c = 0, beg = 0, sl = 0;
     if (lane < nb) {
@@ -762,17 +798,22 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
   if (a.refactor) {
     if (lane == 0) a.pinv[p] = k;
   } else {
-    // claim the pivot row; a row can be claimed twice only by speculative columns
-    int claimed = 1;
-    if (lane == 0) claimed = atomicCAS(&a.pinv[p], -1, k) == -1;
-    claimed = __shfl(claimed, 0, 64);
-    if (!claimed) {
-      if (cx.spec) return 3;
-      if (lane == 0) {
-        atomicMax(&a.status[ST_CODE], DEV_PATTERN);
-        atomicMin(&a.status[ST_FAILCOL], k);
+    // claim the pivot row; a row can be claimed twice only by speculative columns.  A
+    // speculative column stores its claim without waiting for the old value: the check
+    // after the pass finds any row claimed twice (its pivot column is then not k).
+    if (cx.spec) {
+      if (lane == 0) __hip_atomic_store(&a.pinv[p], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int claimed = 1;
+      if (lane == 0) claimed = atomicCAS(&a.pinv[p], -1, k) == -1;
+      claimed = __shfl(claimed, 0, 64);
+      if (!claimed) {
+        if (lane == 0) {
+          atomicMax(&a.status[ST_CODE], DEV_PATTERN);
+          atomicMin(&a.status[ST_FAILCOL], k);
+        }
+        return 2;
       }
-      return 2;
     }
   }
   pre.pp = p;
@@ -790,6 +831,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   wl.key = lds.key; wl.val = lds.val; wl.pv = lds.pv; wl.ins = lds.ins; wl.pj = lds.pj;
   wl.ps = lds.ps; wl.pb = lds.pb; wl.pc = lds.pc; wl.sk = lds.sk; wl.cnt = lds.cnt;
   wl.st_slot = lds.st_slot; wl.st_val = lds.st_val; wl.st_pre = lds.st_pre; wl.st_beg = lds.st_beg;
+  wl.pso = lds.pso;
   wl.H = HS;
   wl.NP = NPS;
   wl.shift = 32 - __builtin_ctz(HS);
@@ -809,6 +851,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.sk = (unsigned long long*)(base + 40ll * H);
     wg.cnt = (int32_t*)(base + 48ll * H);
     wg.st_slot = lds.st_slot; wg.st_val = lds.st_val; wg.st_pre = lds.st_pre; wg.st_beg = lds.st_beg;
+    wg.pso = nullptr;
     wg.H = H;
     wg.NP = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
@@ -913,10 +956,14 @@ template <> struct CoopCfg<4> { static constexpr int H = 512; };
 template <> struct CoopCfg<6> { static constexpr int H = 512; };
 template <> struct CoopCfg<8> { static constexpr int H = 256; };
 
+// dependency lists of up to this many columns are copied to LDS for the checks
+constexpr int kCoopDepsLds = 64;
+
 template <int NW>
 struct CoopLds {
   LdsWs<CoopCfg<NW>::H, CoopCfg<NW>::H / 2, kCoopStage> ws[NW];
   unsigned done[kCoopDoneWords];
+  int32_t deps[NW][kCoopDepsLds];
   int item, slot, bad, skip;
 };
 
@@ -939,6 +986,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
   wl.key = L.key; wl.val = L.val; wl.pv = L.pv; wl.ins = L.ins; wl.pj = L.pj;
   wl.ps = L.ps; wl.pb = L.pb; wl.pc = L.pc; wl.sk = L.sk; wl.cnt = L.cnt;
   wl.st_slot = L.st_slot; wl.st_val = L.st_val; wl.st_pre = L.st_pre; wl.st_beg = L.st_beg;
+  wl.pso = L.pso;
   wl.H = HS;
   wl.NP = HS / 2;
   wl.shift = 32 - __builtin_ctz(HS);
@@ -958,6 +1006,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
     wg.sk = (unsigned long long*)(base + 40ll * H);
     wg.cnt = (int32_t*)(base + 48ll * H);
     wg.st_slot = L.st_slot; wg.st_val = L.st_val; wg.st_pre = L.st_pre; wg.st_beg = L.st_beg;
+    wg.pso = nullptr;
     wg.H = H;
     wg.NP = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
@@ -1053,10 +1102,14 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
         dp = a.dep_idx + a.dep_ptr[k];
         nd = a.dep_ptr[k + 1] - a.dep_ptr[k];
       }
-      // wait for the dependencies (slots of the same segment: slot - (k - j))
+      // wait for the dependencies (slots of the same segment: slot - (k - j)); a short
+      // list is kept in LDS for the column's checks
       bool stalled = false;
+      const bool deps_lds = nd <= kCoopDepsLds;
       for (int e = lane; e < nd; e += 64) {
-        const int js = slot - (k - dp[e]);
+        const int dj = dp[e];
+        if (deps_lds) sm.deps[wv][e] = dj;
+        const int js = slot - (k - dj);
         if (js < sbase || js >= slot) { stalled = true; break; }   // not an earlier column of the segment
         unsigned spins = 0;
         while (!done_bit(sm.done, js)) {
@@ -1077,7 +1130,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
                  ld_relaxed(&a.status[ST_CODE]) != DEV_OK) {
         rc = 2;   // the item is redone, or the factorization has failed: only release waiters
       } else {
-        const ColCtx cx = {a.spec, dp, nd};
+        const ColCtx cx = {a.spec, deps_lds ? sm.deps[wv] : dp, nd};
         const Pre pk = pre;
         rc = factor_column(a, wl, k, al, pre, -1, cx);
         if (rc == 1) {
@@ -1128,6 +1181,11 @@ __global__ void factor_spec_check_kernel(FactorArgs a, int ncols, const int32_t*
   const int k = cols ? cols[t] : t;
   const int it = a.col_item[k];
   if (it < 0 || a.item_bad[it]) return;
+  // the column's pivot row holds its claim (no other column claimed it too)
+  if (a.Ucnt[k] <= 0 || a.pinv[a.piv[k]] != k) {
+    a.item_bad[it] = 1;
+    return;
+  }
   const int b = a.Lbeg[k], c = a.Lcnt[k];
   for (int e = 0; e < c; e++) {
     const int p = a.pinv[a.Li[b + e]];
