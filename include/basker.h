@@ -155,7 +155,7 @@ basker_status basker_symbolic_ordered(int32_t n, const int32_t* colptr, const in
 basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device);
 
 /* Refactorization with new values and the pattern and pivots of the last successful
- * factorization (the symbolic reuse over a matrix sequence of Sec. V-E).  Each
+ * factorization (the symbolic reuse over a matrix sequence of Sec. V-F).  Each
  * column checks |u_kk| >= tau * (largest candidate magnitude) and u_kk != 0; on the
  * first failure the call runs basker_factor and returns BASKER_REFACTOR_FELL_BACK. */
 basker_status basker_refactor(basker_handle h, const double* values, int32_t values_on_device);

@@ -9,7 +9,7 @@ of L, sparse triangular update, pivot selection, copy into L and U) over the
 diagonal blocks of R = A(prow, qcol), with pivots limited to the column's
 candidate group (a BTF block, or a nested-dissection node inside the large
 block, Sec. III-C).  ``refactor`` replays it with the pivots of an earlier
-factorization and a threshold check (Sec. V-E reuses the symbolic analysis over a
+factorization and a threshold check (Sec. V-F reuses the symbolic analysis over a
 matrix sequence).  ``solve`` is block back-substitution over the BTF form
 (Sec. II).  Parity pins for every function live in ``tests/test_oracle_pins.py``.
 """

@@ -15,7 +15,7 @@
  *   - Sec. III-C (fine ND): pivoting is limited to the rows of the column's own
  *     nested-dissection node; rows of ancestor separators are computed into L but
  *     never chosen as pivots for that column.
- *   - Sec. V-E (transient sequence): the symbolic analysis is reused for new
+ *   - Sec. V-F (transient sequence): the symbolic analysis is reused for new
  *     values; the refactor below replays the factorization with the stored pivots.
  *
  * The permuted matrix is R = A(prow, qcol).  Candidate groups are contiguous

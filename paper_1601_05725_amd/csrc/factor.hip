@@ -1,10 +1,10 @@
-// Numeric factorization on gfx950: a persistent kernel in which every wavefront
-// repeatedly takes a ready column from a device queue and runs one column of the
-// left-looking Gilbert-Peierls algorithm (Alg. 1) on it:
+// Numeric factorization on gfx950.  One wavefront runs one column of the left-looking
+// Gilbert-Peierls algorithm (Alg. 1) at a time:
 //
 //   reach     breadth-first closure of struct(R(:,k)) over the graph of L, with the
 //             discovered rows kept in a per-wave LDS hash table (lanes expand the
-//             L columns of a whole frontier at once);
+//             L columns of a whole frontier at once, staging their entries for the
+//             update when they fit);
 //   order     the pivotal rows of the reach sorted by pivot index -- ascending pivot
 //             index is a topological order because every edge of the graph of L runs
 //             from a lower to a higher pivot index;
@@ -12,14 +12,20 @@
 //   pivot     wavefront max-reduction over the candidates (non-pivotal rows of the
 //             column's group), diagonal preference by threshold, smallest index on ties;
 //   store     U(:,k) ascending with the diagonal last, L(:,k) compacted by ballot and
-//             prefix count, both appended to device pools by atomic bump allocation.
+//             prefix count, both appended to device pools by bump allocation of
+//             per-wave chunks.
 //
-// Scheduling follows the level sets of Alg. 4: one launch per level, and in a level
-// every wavefront takes whole segments (a BTF block, or one nested-dissection node)
-// from an atomic counter and factors the segment's columns in order.  Segments of a
-// level are independent (separate blocks, or ND nodes whose pivots stay inside the
-// node), so no wavefront ever waits for another inside a launch; the kernel boundary
-// between levels is the only synchronisation across workgroups.
+// Scheduling follows the level sets of Alg. 4, one launch per level.  The first level
+// (BTF blocks and ND leaves) runs on cooperative workgroups (factor_coop_kernel): a
+// workgroup takes a work item (whole segments) from an atomic counter, and its waves
+// take the item's columns in a level-ordered issue list, each column waiting for the
+// columns of its dependency list through LDS done bits.  A speculative pass uses the
+// dependency lists of the symbolic analysis without row exchanges; every column checks
+// its reach against its list, and a pass over the results redoes any item whose
+// speculation failed with the column elimination tree's safe lists.  Separator levels
+// run one column per wavefront (factor_kernel), a separator's dense block on the dense
+// kernel (sepdense.hip).  The kernel boundary between levels is the only
+// synchronisation across workgroups.
 //
 // Arithmetic matches a serial run that updates in ascending pivot order: every update
 // is a separately rounded multiply and subtract (built with -ffp-contract=off),
