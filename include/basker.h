@@ -123,6 +123,13 @@ typedef struct {
                                     check after the last factorization sent back to plain row order */
   double rows_kernel_ms;     /* device time of the row-wise copies of L and U built after the last
                                 successful factor/refactor (used by the solve) */
+  int64_t sym_lnz;           /* nnz(L) and nnz(U) of a factorization without row exchanges, from the
+                                symbolic analysis (0 when its budget ran out) */
+  int64_t sym_unz;
+  int32_t fill_bound;        /* 1 when the symbolic analysis finished within its budget, so the two
+                                counts above and sym_ws_rows hold; 0 when the budget ran out */
+  int32_t sym_ws_rows;       /* largest column workspace (rows of one column's reach, a separator's
+                                first step included) without row exchanges */
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */
@@ -151,7 +158,10 @@ basker_status basker_symbolic_ordered(int32_t n, const int32_t* colptr, const in
 /* Numeric factorization (Alg. 1 per column over the BTF blocks, Sec. III-B, and the
  * ND nodes, Alg. 4) with the values of A in the symbolic call's CSC order.
  * values is a host pointer, or a device pointer when values_on_device != 0.
- * Returns after the factorization is complete. */
+ * Returns after the factorization is complete.  Before any device work (also on an
+ * analysis-only handle), a plan in which a column's reach without row exchanges exceeds
+ * the per-wave workspace (basker_info sym_ws_rows above 8,192 rows, known when
+ * fill_bound is 1) fails with BASKER_ERR_WORKSPACE. */
 basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device);
 
 /* Refactorization with new values and the pattern and pivots of the last successful

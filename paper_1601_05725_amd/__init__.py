@@ -54,7 +54,9 @@ class basker_info_t(ctypes.Structure):
                 ("dense_seps", ctypes.c_int32), ("sparse_seps", ctypes.c_int32),
                 ("device_bytes_plan", ctypes.c_int64), ("coop_items", ctypes.c_int32),
                 ("coop_waves", ctypes.c_int32), ("redo_items", ctypes.c_int32), ("learn_events", ctypes.c_int32),
-                ("solve_order_fallbacks", ctypes.c_int32), ("rows_kernel_ms", ctypes.c_double)]
+                ("solve_order_fallbacks", ctypes.c_int32), ("rows_kernel_ms", ctypes.c_double),
+                ("sym_lnz", ctypes.c_int64), ("sym_unz", ctypes.c_int64), ("fill_bound", ctypes.c_int32),
+                ("sym_ws_rows", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}

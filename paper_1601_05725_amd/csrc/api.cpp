@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -600,6 +602,10 @@ static void fill_info_static(basker_ctx* h) {
   I.device_bytes_plan = plan_device_bytes(P, h->opt);
   I.coop_items = coop_usable(P) ? (int32_t)P.co_item_lo.size() : 0;
   I.coop_waves = coop_waves_of(h->opt);
+  I.fill_bound = P.sym_ok ? 1 : 0;
+  I.sym_lnz = P.sym_ok ? P.sym_lnz : 0;
+  I.sym_unz = P.sym_ok ? P.sym_unz : 0;
+  I.sym_ws_rows = P.sym_ok ? (int32_t)std::min<int64_t>(P.sym_ws_max, INT32_MAX) : 0;
 }
 
 extern "C" basker_status basker_symbolic(int32_t n, const int32_t* colptr, const int32_t* rowind, const double* values,
@@ -710,8 +716,40 @@ static basker_status stage_values(basker_ctx* h, const double* values, int32_t o
 }
 
 // the launches of one device pass (init, then every level); returns the first error
+// BASKER_TRACE_LEVELS=1 in the environment: every factor level is waited for and its
+// completion reported on stderr (level, elapsed time, status word), for following a long
+// factorization as it runs.  Ignored while the stream is being captured.
+static bool trace_levels() {
+  static const bool on = [] {
+    const char* v = std::getenv("BASKER_TRACE_LEVELS");
+    return v != nullptr && v[0] != '\0' && v[0] != '0';
+  }();
+  return on;
+}
+
+static double now_ms() {
+  return (double)std::chrono::duration_cast<std::chrono::microseconds>(
+             std::chrono::steady_clock::now().time_since_epoch()).count() / 1000.0;
+}
+static thread_local double trace_t0 = 0.0;
+
+static hipError_t trace_level_done(basker_ctx* h, int l, const char* what) {
+  if (!trace_levels()) return hipSuccess;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return e;
+  int32_t code = 0;
+  e = hipMemcpy(&code, h->status.p + ST_CODE, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  std::fprintf(stderr, "basker: factor level %d %s done at %.1f ms, status %d\n", l, what, now_ms() - trace_t0, code);
+  std::fflush(stderr);
+  return hipSuccess;
+}
+
 static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
   hipStream_t s = h->stream;
+  if (trace_levels()) trace_t0 = now_ms();
   FactorArgs a = factor_args(h, refactor);
   const Plan& P = h->plan;
   const int nlev = (int)P.lvl_ptr.size() - 1;
@@ -769,6 +807,7 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
           if ((e = launch_factor_coop(a, h->coop_waves, h->coop_grid, s)) != hipSuccess) return e;
           a.redo = 0;
         }
+        if ((e = trace_level_done(h, 0, "first level")) != hipSuccess) return e;
         continue;
       }
       const int grid = std::min(a.item_end - a.item_begin, h->grid);
@@ -798,6 +837,7 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     }
     dA.d_begin = P.lvl_dsep_ptr[l];
     if ((e = launch_sepdense(dA, P.lvl_dsep_ptr[l + 1] - P.lvl_dsep_ptr[l], s)) != hipSuccess) return e;
+    if ((e = trace_level_done(h, l, "separator")) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -962,7 +1002,7 @@ static basker_status do_factor(basker_ctx* h) {
     }
     h->factored = false;
     if (st[ST_CODE] == DEV_POOL && st[ST_CBPOOL]) {
-      int64_t need = std::max<int64_t>((int64_t)poolc[2] * 2, 2 * h->cbI.cap);
+      int64_t need = std::max<int64_t>((int64_t)poolc[2] * 4, 4 * h->cbI.cap);
       if (need > 0x7fffffffLL) need = 0x7fffffffLL;
       if (need <= h->cbI.cap) return fail(h, BASKER_ERR_OOM, "separator buffer exceeds 2^31 entries");
       HIPCHK(h, h->cbI.reserve(need));
@@ -971,11 +1011,12 @@ static basker_status do_factor(basker_ctx* h) {
       continue;
     }
     if (st[ST_CODE] == DEV_POOL) {
-      // grow the pool(s) that ran out to twice the demand seen so far
+      // grow the pool(s) that ran out to four times the demand seen so far (every growth
+      // repeats the pass, and the demand seen is only what the pass reached)
       bool grew = false;
       const bool l_over = (int64_t)poolc[0] > h->Li.cap, u_over = (int64_t)poolc[1] > h->Ui.cap;
       if (l_over || !u_over) {
-        int64_t need = std::min<int64_t>(std::max<int64_t>((int64_t)poolc[0] * 2, 2 * h->Li.cap), 0x7fffffffLL);
+        int64_t need = std::min<int64_t>(std::max<int64_t>((int64_t)poolc[0] * 4, 4 * h->Li.cap), 0x7fffffffLL);
         if (need > h->Li.cap) {
           HIPCHK(h, h->Li.reserve(need));
           HIPCHK(h, h->Lx.reserve(need));
@@ -983,7 +1024,7 @@ static basker_status do_factor(basker_ctx* h) {
         }
       }
       if (u_over || !l_over) {
-        int64_t need = std::min<int64_t>(std::max<int64_t>((int64_t)poolc[1] * 2, 2 * h->Ui.cap), 0x7fffffffLL);
+        int64_t need = std::min<int64_t>(std::max<int64_t>((int64_t)poolc[1] * 4, 4 * h->Ui.cap), 0x7fffffffLL);
         if (need > h->Ui.cap) {
           HIPCHK(h, h->Ui.reserve(need));
           HIPCHK(h, h->Ux.reserve(need));
@@ -1003,9 +1044,24 @@ static basker_status do_factor(basker_ctx* h) {
   return fail(h, BASKER_ERR_OOM, "L/U pool growth did not converge");
 }
 
+// A plan the numeric kernels cannot run is refused before any device work: a column
+// whose reach without row exchanges exceeds the per-wave global workspace (known when
+// the symbolic analysis finished within its budget; otherwise the kernels detect an
+// overflow as they go).
+static basker_status plan_guard(basker_ctx* h) {
+  const Plan& P = h->plan;
+  if (P.sym_ok && P.sym_ws_max > kGwsSlots / 2)
+    return fail(h, BASKER_ERR_WORKSPACE,
+                "a column's reach without row exchanges (" + std::to_string(P.sym_ws_max) +
+                    " rows) exceeds the per-wave workspace (" + std::to_string(kGwsSlots / 2) + " rows)");
+  return BASKER_OK;
+}
+
 extern "C" basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device) {
   if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
   AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
+  const basker_status g = plan_guard(h);
+  if (g != BASKER_OK) return g;
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   HIPCHK(h, hipSetDevice(h->device));
   basker_status r = stage_values(h, values, values_on_device);

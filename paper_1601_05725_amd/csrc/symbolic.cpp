@@ -1320,6 +1320,7 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
   P.co_max_item_cols = 0;
   P.sym_ok = false;
   P.sym_lnz = P.sym_unz = P.sym_cb = 0;
+  P.sym_ws_max = 0;
   if (nlev < 1 || n == 0) {
     P.sym_ok = true;
     P.sfo.clear();
@@ -1419,8 +1420,10 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
         // the separator first step: descendants' pivots only (rows before the separator)
         closure(k, g0, ++stamp);
         P.sym_cb += (int64_t)queue.size();
+        P.sym_ws_max = std::max<int64_t>(P.sym_ws_max, (int64_t)queue.size());
       }
       closure(k, k, ++stamp);
+      P.sym_ws_max = std::max<int64_t>(P.sym_ws_max, (int64_t)queue.size());
       int64_t lc = 0, uc = 1;
       deps.clear();
       for (int i : queue) {

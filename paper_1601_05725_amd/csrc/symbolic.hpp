@@ -109,6 +109,7 @@ struct Plan {
   // the L/U pools and the separator buffer); sym_ok false when the pass was cut short
   bool sym_ok = false;
   int64_t sym_lnz = 0, sym_unz = 0, sym_cb = 0;
+  int64_t sym_ws_max = 0;   // largest reach (rows of one column's workspace), separator first steps included
   int struct_rank = 0;
   double bottleneck = 0.0;
   int max_depth = 0;

@@ -235,3 +235,46 @@ def test_device_bytes_plan_estimate(bk):
     small = analyse(bk, a, capacity_factor=2.0).info()["device_bytes_plan"]
     big = analyse(bk, a, capacity_factor=6.0).info()["device_bytes_plan"]
     assert big - small >= 2 * 12 * int(4.0 * analyse(bk, a).info()["nnz_diag"]) - 64
+
+
+def _diag_dominant(n, density, seed):
+    a = synth.random_sparse(n, density, seed=seed)
+    d = a.to_dense()
+    np.fill_diagonal(d, np.abs(d).sum(axis=1) + 1.0)
+    return synth.csc_from_dense(d)
+
+
+@pytest.mark.parametrize("n,seed,kw", [(300, 11, {}), (900, 12, {"nd_min_block": 400, "nd_leaves": 4})])
+def test_fill_bound_is_the_fill_without_row_exchanges(bk, n, seed, kw):
+    """The analysis's fill counts are the factorization's when no row leaves the
+    diagonal: on a diagonally dominant matrix the oracle (same ordering) pivots on the
+    diagonal, and its nnz(L), nnz(U) equal the reported bound."""
+    import oracle
+    a = _diag_dominant(n, 0.01, seed)
+    h = analyse(bk, a, **kw)
+    inf = h.info()
+    assert inf["fill_bound"] == 1
+    prow, qcol, bp, gp = h.ordering()
+    f = oracle.factor(a, oracle.Ordering(prow, qcol, bp, gp), update_order=oracle.ORDER_ASCENDING)
+    assert f.status == oracle.OK
+    assert np.array_equal(f.piv, np.arange(n))   # no row exchange
+    assert inf["sym_lnz"] == f.lnz and inf["sym_unz"] == f.unz
+    # a column's workspace holds its L and U rows: at least the longest column of L + U
+    longest = max(int(f.Lp[k + 1] - f.Lp[k] + f.Up[k + 1] - f.Up[k]) for k in range(n))
+    assert inf["sym_ws_rows"] >= longest
+
+
+def test_factor_refuses_a_column_beyond_the_workspace(bk):
+    """An arrow matrix whose dense column reaches 9,000 rows exceeds the 8,192-row
+    per-wave workspace: basker_factor refuses it before any device work."""
+    n = 9000
+    r = np.concatenate([np.arange(n), np.arange(n - 1), np.full(n - 1, n - 1)])
+    c = np.concatenate([np.arange(n), np.full(n - 1, n - 1), np.arange(n - 1)])
+    v = np.concatenate([np.full(n, 4.0), np.ones(2 * (n - 1))])
+    a = synth.csc_from_coo(n, r, c, v)
+    h = analyse(bk, a, nd_min_block=1 << 30)
+    inf = h.info()
+    assert inf["fill_bound"] == 1 and inf["sym_ws_rows"] > 8192
+    with pytest.raises(bk.BaskerError) as e:
+        h.factor(a.values)
+    assert e.value.status == bk.ERR_WORKSPACE
