@@ -80,7 +80,13 @@ typedef struct {
   int32_t item_cols;       /* first-level work items hold at least this many columns unless a
                               block or ND leaf is larger (0 = 256) */
   int32_t coop_waves;      /* wavefronts per workgroup of the first level: 4, 6 or 8 (0 = 6) */
-  int32_t reserved[1];
+  int32_t bin_edge;        /* size bins of the first level (Sec. III-B's fine BTF blocks): 1 x 1
+                              blocks take one thread each, segments of 2..bin_edge columns one
+                              wavefront each, larger ones share a workgroup's wavefronts
+                              (0 = 32; -1 = no wavefront bin) */
+  int32_t autotune;        /* 1: the first factorizations try the bin edges and wavefront counts
+                              and keep the fastest (basker_info reports the choice); results do
+                              not depend on it (default 0) */
 } basker_options;
 
 typedef struct {

@@ -37,7 +37,8 @@ class basker_options(ctypes.Structure):
                 ("nd_min_block", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("refactor_graph", ctypes.c_int32),
                 ("max_grid", ctypes.c_int32), ("hbm_budget", ctypes.c_int64), ("sched_flags", ctypes.c_int32),
-                ("item_cols", ctypes.c_int32), ("coop_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("item_cols", ctypes.c_int32), ("coop_waves", ctypes.c_int32), ("bin_edge", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class basker_info_t(ctypes.Structure):

@@ -93,7 +93,7 @@ struct basker_ctx {
   DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, grpptr;
   // first-level cooperative schedule
   DBuf<int32_t> co_item_lo, co_item_hi, co_item_cols, col_item, dep_ptr, dep_idx, sdep_ptr, sdep_idx, item_bad;
-  DBuf<int32_t> co_item_off, co_issue;
+  DBuf<int32_t> co_item_off, co_issue, co_item_kind;
   bool coop = false;
   int coop_waves = 6;
   int coop_grid = 0;
@@ -169,6 +169,7 @@ static bool options_valid(const basker_options& o) {
   if (o.nd_leaves < 1 || (o.nd_leaves & (o.nd_leaves - 1)) != 0) return false;
   if (o.hbm_budget < 0 || o.max_grid < 0 || o.item_cols < 0 || o.capacity_factor < 0) return false;
   if (o.coop_waves != 0 && o.coop_waves != 4 && o.coop_waves != 6 && o.coop_waves != 8) return false;
+  if (o.bin_edge < -1 || o.autotune < 0 || o.autotune > 1) return false;
   return true;
 }
 
@@ -225,6 +226,8 @@ static int coop_grid_of(const Plan& P, const basker_options& o, int waves) {
 }
 
 static int coop_waves_of(const basker_options& o) { return o.coop_waves ? o.coop_waves : 6; }
+constexpr int kDefaultBinEdge = 32;
+static int bin_edge_of(const basker_options& o) { return o.bin_edge == 0 ? kDefaultBinEdge : (o.bin_edge < 0 ? 0 : o.bin_edge); }
 
 // Every first-level column in exactly one item with a slot count that matches its
 // segments, and every dependency list ascending inside the column's own segment
@@ -362,7 +365,7 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   const int64_t nco = (int64_t)P.co_item_lo.size();
   add(4, nco); add(4, nco); add(4, nco); add(4, n); add(4, nco);   // items, col_item, item_bad
   add(4, n + 1); add(4, (int64_t)P.dep_idx.size()); add(4, n + 1); add(4, (int64_t)P.sdep_idx.size());
-  add(4, (int64_t)P.co_item_off.size()); add(4, (int64_t)P.co_issue.size());
+  add(4, (int64_t)P.co_item_off.size()); add(4, (int64_t)P.co_issue.size()); add(4, nco);
   const int64_t nrhs = 8;
   add(8, n * nrhs); add(8, n * nrhs); add(8, n * nrhs);            // W, Z, Bdev
   // row-wise factors: keys and values, sorted copies, sort workspace, over the fill
@@ -539,6 +542,7 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->item_bad.reserve((int64_t)P.co_item_lo.size()));
   HIPCHK(h, h->co_item_off.upload(P.co_item_off, s));
   HIPCHK(h, h->co_issue.upload(P.co_issue, s));
+  HIPCHK(h, h->co_item_kind.upload(P.co_item_kind, s));
   HIPCHK(h, hipStreamSynchronize(s));
   return BASKER_OK;
 }
@@ -626,7 +630,7 @@ extern "C" basker_status basker_symbolic(int32_t n, const int32_t* colptr, const
     basker_free(h);
     return s;
   }
-  build_level0_schedule(h->plan, h->opt.item_cols ? h->opt.item_cols : 256, kSymVisitBudget);
+  build_level0_schedule(h->plan, h->opt.item_cols ? h->opt.item_cols : 256, kSymVisitBudget, bin_edge_of(h->opt));
   h->plan.co_valid = level0_schedule_valid(h->plan);
   if (h->device >= 0) {
     st = upload_plan(h);
@@ -647,7 +651,7 @@ extern "C" basker_status basker_symbolic_ordered(int32_t n, const int32_t* colpt
   if (st != BASKER_OK) return st;
   int rc = build_plan_user(n, colptr, rowind, prow, qcol, nblocks, blkptr, ngroups, grpptr, h->plan);
   if (rc != 0) { basker_free(h); return BASKER_ERR_INVALID; }
-  build_level0_schedule(h->plan, h->opt.item_cols ? h->opt.item_cols : 256, kSymVisitBudget);
+  build_level0_schedule(h->plan, h->opt.item_cols ? h->opt.item_cols : 256, kSymVisitBudget, bin_edge_of(h->opt));
   h->plan.co_valid = level0_schedule_valid(h->plan);
   if (h->device >= 0) {
     st = upload_plan(h);
@@ -691,6 +695,7 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.gws = h->gws.p; a.gws_stride = h->gws_stride; a.gws_slots = h->gws_slots;
   a.reverse = h->opt.sched_flags & 1;
   a.co_item_lo = h->co_item_lo.p; a.co_item_hi = h->co_item_hi.p; a.co_item_cols = h->co_item_cols.p;
+  a.co_item_kind = h->co_item_kind.p;
   a.col_item = h->col_item.p;
   a.item_bad = h->item_bad.p;
   a.co_item_off = h->co_item_off.p;

@@ -107,6 +107,7 @@ struct FactorArgs {
   int32_t spec;
   int32_t redo;
   int32_t* item_bad;
+  const int32_t* co_item_kind;  // size bin of every item: 0 shared columns, 1 wave per segment, 2 thread per 1 x 1 block
   const int32_t* co_item_off;   // first issue entry of every item
   const int32_t* co_issue;      // (column, slot, segment start) in the issue order of the speculative pass
   int32_t use_issue;            // 1: take columns from co_issue; 0: in slot order

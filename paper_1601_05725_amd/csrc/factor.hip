@@ -971,6 +971,7 @@ struct CoopLds {
   unsigned done[kCoopDoneWords];
   int32_t deps[NW][kCoopDepsLds];
   int item, slot, bad, skip;
+  unsigned long long ubase;
 };
 
 __device__ __forceinline__ bool done_bit(const unsigned* done, int slot) {
@@ -1041,6 +1042,87 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
     const int it = sm.item;
     if (it < 0) break;
     if (sm.skip) continue;
+    const int kind = a.co_item_kind ? a.co_item_kind[it] : 0;
+    if (kind == 2) {
+      // 1 x 1 diagonal blocks, one thread each: the pivot is the block's only entry; U
+      // takes one entry per column from one pool allocation for the item
+      const int lo = a.co_item_lo[it], cnt = a.co_item_hi[it] - lo;
+      if (!a.refactor) {
+        if (tid == 0) {
+          sm.ubase = atomicAdd(&a.pool_next[1], (unsigned long long)cnt);
+          if ((long long)sm.ubase + cnt > a.Ucap) {
+            atomicMax(&a.status[ST_CODE], DEV_POOL);
+            a.status[ST_POOL] = 1;
+          }
+          al.unz += cnt;
+        }
+        __syncthreads();
+        if ((long long)sm.ubase + cnt > a.Ucap) continue;
+      }
+      for (int i = tid; i < cnt; i += 64 * NW) {
+        const int k = a.seg_c0[a.lvl_seg[lo + i]];
+        const double x = a.Rx[a.Rp[k]];
+        if (!a.refactor) {
+          if (!(fabs(x) > 0.0)) {
+            atomicMax(&a.status[ST_CODE], DEV_SINGULAR);
+            atomicMin(&a.status[ST_FAILCOL], k);
+            continue;
+          }
+          const int ub = (int)(sm.ubase + (unsigned long long)i);
+          a.Ui[ub] = k;
+          a.Ux[ub] = x;
+          a.Ubeg[k] = ub;
+          a.Ucnt[k] = 1;
+          a.Lbeg[k] = 0;
+          a.Lcnt[k] = 0;
+          a.piv[k] = k;
+          a.pinv[k] = k;
+        } else {
+          if (!(fabs(x) > 0.0) || a.Ucnt[k] != 1 || a.piv[k] != k) {
+            atomicMax(&a.status[ST_CODE], DEV_REFACTOR_FAIL);
+            atomicMin(&a.status[ST_FAILCOL], k);
+            continue;
+          }
+          a.Ux[a.Ubeg[k]] = x;
+          a.pinv[k] = k;
+        }
+      }
+      continue;
+    }
+    if (kind == 1) {
+      // segments of the small bin: one wavefront factors a whole segment column by
+      // column (serial Gilbert-Peierls inside the segment; no waits between waves)
+      const ColCtx cx0 = {0, nullptr, 0};
+      const int lo = a.co_item_lo[it], nseg = a.co_item_hi[it] - lo;
+      while (true) {
+        int qi = 0;
+        if (lane == 0) qi = atomicAdd(&sm.slot, 1);
+        qi = __shfl(qi, 0, 64);
+        if (qi >= nseg) break;
+        if (ld_relaxed(&a.status[ST_CODE]) != DEV_OK) continue;
+        const int sg = a.lvl_seg[lo + qi];
+        const int c0 = a.seg_c0[sg], c1 = a.seg_c1[sg];
+        pre.k = -1;
+        pre.fresh = 0;
+        for (int k = c0; k < c1; k++) {
+          const int knext = k + 1 < c1 ? k + 1 : -1;
+          const Pre pk = pre;
+          int rc = factor_column(a, wl, k, al, pre, knext, cx0);
+          if (rc == 1) {
+            pre = pk;
+            rc = factor_column(a, wg, k, al, pre, knext, cx0);
+            if (rc == 1 && lane == 0) {
+              atomicMax(&a.status[ST_CODE], DEV_WORKSPACE);
+              atomicMin(&a.status[ST_FAILCOL], k);
+              a.status[ST_WS] = 1;
+            }
+          }
+          if (rc != 0) break;
+          wsync();
+        }
+      }
+      continue;
+    }
     const int ncols = a.co_item_cols[it];
     for (int w = tid; w < ((ncols + 31) >> 5); w += 64 * NW) sm.done[w] = 0u;
     if (a.redo) {

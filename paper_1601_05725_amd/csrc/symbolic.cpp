@@ -1310,10 +1310,59 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
 // exchanges can change these sets, which the device detects; the column elimination
 // tree gives lists that hold for every pivot sequence (George and Ng).
 // ---------------------------------------------------------------------------
-void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
+void build_level0_items(Plan& P, int co_min_cols, int bin_edge) {
+  const int n = P.n;
+  P.co_item_lo.clear(); P.co_item_hi.clear(); P.co_item_cols.clear(); P.co_item_kind.clear();
+  P.col_item.assign(n, -1);
+  P.co_max_item_cols = 0;
+  P.co_bin_edge = bin_edge;
+  const int nlev = (int)P.lvl_ptr.size() - 1;
+  if (nlev < 1 || n == 0) return;
+  // bin of a segment: 2 = a 1 x 1 diagonal block (its column of R is the diagonal), 1 =
+  // at most bin_edge columns (one wavefront factors it column by column), 0 = larger
+  auto bin_of = [&](int sg) {
+    const int c0 = P.seg_c0[sg], sz = P.seg_c1[sg] - c0;
+    if (sz == 1 && P.Rp[c0 + 1] - P.Rp[c0] == 1 && P.Ri[P.Rp[c0]] == c0) {
+      const int b = (int)(std::upper_bound(P.blkptr.begin(), P.blkptr.end(), c0) - P.blkptr.begin()) - 1;
+      if (P.blkptr[b] == c0 && P.blkptr[b + 1] == c0 + 1) return 2;
+    }
+    return sz <= bin_edge ? 1 : 0;
+  };
+  // items over level 0 (lvl_seg is largest first inside a level); an item holds one bin
+  const int q0 = P.lvl_ptr[0], q1 = P.lvl_ptr[1];
+  int start = q0, acc = 0, kind = -1;
+  auto close = [&](int q) {
+    if (q > start) {
+      P.co_item_lo.push_back(start); P.co_item_hi.push_back(q); P.co_item_cols.push_back(acc);
+      P.co_item_kind.push_back(kind);
+    }
+    start = q;
+    acc = 0;
+  };
+  for (int q = q0; q < q1; q++) {
+    const int sg = P.lvl_seg[q];
+    const int sz = P.seg_c1[sg] - P.seg_c0[sg];
+    const int kq = bin_of(sg);
+    if (kq != kind) {
+      close(q);
+      kind = kq;
+    } else if (kq == 2 ? acc >= kBin1ItemCols : (acc > 0 && (acc >= co_min_cols || sz >= co_min_cols))) {
+      close(q);
+    }
+    acc += sz;
+  }
+  close(q1);
+  for (size_t it = 0; it < P.co_item_lo.size(); it++) {
+    P.co_max_item_cols = std::max(P.co_max_item_cols, P.co_item_cols[it]);
+    for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++)
+      for (int k = P.seg_c0[P.lvl_seg[q]]; k < P.seg_c1[P.lvl_seg[q]]; k++) P.col_item[k] = (int32_t)it;
+  }
+}
+
+void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget, int bin_edge) {
   const int n = P.n;
   const int nlev = (int)P.lvl_ptr.size() - 1;
-  P.co_item_lo.clear(); P.co_item_hi.clear(); P.co_item_cols.clear();
+  P.co_item_lo.clear(); P.co_item_hi.clear(); P.co_item_cols.clear(); P.co_item_kind.clear();
   P.col_item.assign(n, -1);
   P.dep_ptr.assign(n + 1, 0); P.dep_idx.clear();
   P.sdep_ptr.assign(n + 1, 0); P.sdep_idx.clear();
@@ -1331,26 +1380,7 @@ void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget) {
   std::vector<int32_t> col_seg(n, -1);
   for (size_t sg = 0; sg < P.seg_c0.size(); sg++)
     for (int k = P.seg_c0[sg]; k < P.seg_c1[sg]; k++) col_seg[k] = (int32_t)sg;
-  // items over level 0 (lvl_seg is largest first inside a level)
-  {
-    int q0 = P.lvl_ptr[0], q1 = P.lvl_ptr[1];
-    int start = q0, acc = 0;
-    for (int q = q0; q < q1; q++) {
-      const int sz = P.seg_c1[P.lvl_seg[q]] - P.seg_c0[P.lvl_seg[q]];
-      if (acc > 0 && (acc >= co_min_cols || sz >= co_min_cols)) {
-        P.co_item_lo.push_back(start); P.co_item_hi.push_back(q); P.co_item_cols.push_back(acc);
-        start = q;
-        acc = 0;
-      }
-      acc += sz;
-    }
-    if (q1 > start) { P.co_item_lo.push_back(start); P.co_item_hi.push_back(q1); P.co_item_cols.push_back(acc); }
-    for (size_t it = 0; it < P.co_item_lo.size(); it++) {
-      P.co_max_item_cols = std::max(P.co_max_item_cols, P.co_item_cols[it]);
-      for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++)
-        for (int k = P.seg_c0[P.lvl_seg[q]]; k < P.seg_c1[P.lvl_seg[q]]; k++) P.col_item[k] = (int32_t)it;
-    }
-  }
+  build_level0_items(P, co_min_cols, bin_edge);
   // safe lists: children in the column elimination tree, inside the segment
   {
     std::vector<int32_t> cnt(n + 1, 0);

@@ -87,7 +87,11 @@ struct Plan {
   // without row exchanges, or learned from an earlier factorization), and the safe
   // one, sdep_* (its children in the column elimination tree, which bounds the
   // dependencies of every pivot sequence).
-  std::vector<int32_t> co_item_lo, co_item_hi, co_item_cols;
+  // Items hold one size bin each (co_item_kind): 0 = segments above the bin edge, whose
+  // columns the waves share as above; 1 = segments of at most co_bin_edge columns, one
+  // wavefront factoring a whole segment; 2 = 1 x 1 diagonal blocks, one thread each.
+  std::vector<int32_t> co_item_lo, co_item_hi, co_item_cols, co_item_kind;
+  int32_t co_bin_edge = 0;
   std::vector<int32_t> col_item;              // level-0 column -> item (-1 elsewhere)
   std::vector<int32_t> dep_ptr, dep_idx, sdep_ptr, sdep_idx;
   int32_t co_max_item_cols = 0;
@@ -133,7 +137,14 @@ int build_plan_user(int n, const int32_t* Ap, const int32_t* Ai,
 
 // Level-0 items and dependency lists, and the fill of a factorization without row
 // exchanges (within a budget of visited pattern entries).
-void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget);
+void build_level0_schedule(Plan& P, int co_min_cols, int64_t visit_budget, int bin_edge);
+
+// The first level's work items (bins and grouping) alone, for a new bin edge or item
+// size: the dependency lists are kept; build_issue_order must follow.
+void build_level0_items(Plan& P, int co_min_cols, int bin_edge);
+
+// columns of a work item of 1 x 1 blocks (one thread each)
+constexpr int kBin1ItemCols = 2048;
 
 // Issue order of every item from the predicted lists (after they change).
 void build_issue_order(Plan& P);

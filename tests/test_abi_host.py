@@ -213,14 +213,33 @@ def test_options_rejected(bk, field, value):
     assert e.value.status == bk.ERR_INVALID
 
 
-def test_options_struct_layout(bk):
-    """The binding's structs match the header: offsets of the fields after the pointer."""
+def _c_layout(struct, fields):
+    """sizeof and offsetof of the header's struct, from the C compiler."""
+    import subprocess
+    import tempfile
+    body = "\n".join('printf("%%s %%zu\\n", "%s", offsetof(%s, %s));' % (f, struct, f) for f in fields)
+    src = ('#include <stddef.h>\n#include <stdio.h>\n#include "basker.h"\nint main(void) {\n'
+           'printf("sizeof %%zu\\n", sizeof(%s));\n%s\nreturn 0;\n}\n' % (struct, body))
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return {out[i]: int(out[i + 1]) for i in range(0, len(out), 2)}
+
+
+@pytest.mark.parametrize("name", ["basker_options", "basker_info_t"])
+def test_struct_layouts_match_the_header(bk, name):
+    """Every field of the binding's ctypes structs sits where the C compiler puts the
+    header's field, and the sizes agree."""
+    cls = getattr(bk, name)
+    fields = [f for f, _ in cls._fields_]
+    lay = _c_layout(name, fields)
     import ctypes
-    o = bk.basker_options
-    assert ctypes.sizeof(o) == 88
-    assert o.stream.offset == 48 and o.refactor_graph.offset == 56 and o.max_grid.offset == 60
-    assert o.hbm_budget.offset == 64 and o.sched_flags.offset == 72
-    assert bk.basker_info_t.device_bytes_plan.offset % 8 == 0
+    assert lay["sizeof"] == ctypes.sizeof(cls)
+    for f in fields:
+        assert lay[f] == getattr(cls, f).offset, f
 
 
 def test_device_bytes_plan_estimate(bk):

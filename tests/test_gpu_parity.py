@@ -502,3 +502,47 @@ def test_first_level_schedules_agree(bk, orc, waves, flags, item_cols):
     say("waves %d flags %d items %d redo %d" % (waves, flags, inf["coop_items"], inf["redo_items"]))
     assert inf["coop_items"] > 1 and inf["coop_waves"] == waves
     compare_exact(h.extract(), orc.factor(a, order, update_order=orc.ORDER_ASCENDING))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bin_edge", [-1, 4, 64, 4096])
+def test_first_level_bins_agree(bk, orc, bin_edge):
+    """Size bins of the first level (thread per 1 x 1 block, wavefront per segment of at
+    most bin_edge columns, shared workgroups above it) change who factors which column;
+    factorization and refactorization stay the oracle's bit for bit."""
+    inp = synth.gen_batched_btf(nblocks=600, big=6000, seed=23)
+    a = inp.a
+    o = bk.default_options(nd_min_block=3000, nd_leaves=8, bin_edge=bin_edge)
+    h = bk.Handle.symbolic(a, o)
+    prow, qcol, bp, gp = h.ordering()
+    order = orc.Ordering(prow, qcol, bp, gp)
+    say("bin_edge %d: items %d" % (bin_edge, h.info()["coop_items"]))
+    h.factor(a.values)
+    e0 = h.extract()
+    compare_exact(e0, orc.factor(a, order, update_order=orc.ORDER_ASCENDING))
+    vals = next(iter(synth.value_sequence(a, 1, sigma=0.002)))
+    st = h.refactor(vals)
+    ref = orc.refactor(a.with_values(vals), order, e0.piv, update_order=orc.ORDER_ASCENDING)
+    if ref.status == 0:
+        assert st == bk.OK
+        compare_exact(h.extract(), ref)
+
+
+@pytest.mark.gpu
+def test_one_by_one_block_singular(bk, orc):
+    """A 1 x 1 diagonal block holding an explicit zero is numerically singular: the
+    thread-per-block bin reports it at that column, like the oracle."""
+    # diagonal with an explicit zero at (2, 2), and one coupling entry (0, 5)
+    r = np.array([0, 1, 2, 3, 4, 5, 0])
+    c = np.array([0, 1, 2, 3, 4, 5, 5])
+    v = np.array([2.0, 3.0, 0.0, 4.0, 5.0, 1.5, 1.0])
+    a = synth.csc_from_coo(6, r, c, v)
+    assert a.nnz == 7
+    h = bk.Handle.symbolic(a, bk.default_options(matching=0))
+    prow, qcol, bp, gp = h.ordering()
+    f = orc.factor(a, orc.Ordering(prow, qcol, bp, gp))
+    assert f.status != 0
+    with pytest.raises(bk.BaskerError) as e:
+        h.factor(a.values)
+    assert e.value.status == bk.ERR_NUM_SINGULAR
+    assert h.info()["fail_col"] == f.fail_col
