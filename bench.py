@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--patterns", type=int, default=16, help="c4: distinct patterns")
     ap.add_argument("--nmax", type=int, default=100000, help="c4: largest pattern order (smallest 1,000)")
     ap.add_argument("--slots", type=int, default=8, help="c4: concurrent requests")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default first-level schedule instead of timing the candidates before the run")
     ap.add_argument("--saturate", type=int, default=4, metavar="K",
                     help="saturated leg: K handles of the workload, each factor+solve loop in its own host "
                          "thread on one of min(K, 4) streams (0: skip)")
@@ -173,6 +175,8 @@ def main():
     a, cfg, opts = make_workload(args.workload)
     log("workload %s n=%d nnz=%d generated in %.1fs" % (cfg["workload"], a.n, a.nnz, time.perf_counter() - t))
     t = time.perf_counter()
+    if not args.no_autotune:
+        opts = dict(opts, autotune=1)
     h = bk.Handle.symbolic(a, bk.default_options(**opts))
     info = h.info()
     log("symbolic %.1fs: blocks=%d groups=%d nd_blocks=%d levels=%d crit_cols=%d" % (
@@ -194,6 +198,16 @@ def main():
     info = h.info()
     log("first factor: lnz=%d unz=%d kernel %.2f ms regrows=%d" % (info["lnz"], info["unz"],
                                                                      info["factor_kernel_ms"], info["pool_regrows"]))
+    if not args.no_autotune and not refactor:
+        # the autotuner times its schedule candidates on the next factorizations
+        t = time.perf_counter()
+        for _ in range(16):
+            h.factor(vals0)
+            if h.info()["autotune_trials"] >= 7:
+                break
+        info = h.info()
+        log("autotune: %d candidates in %.1fs -> bin edge %d, %d waves per workgroup" % (
+            info["autotune_trials"], time.perf_counter() - t, info["sched_bin_edge"], info["coop_waves"]))
 
     def step(i):
         if refactor:
@@ -264,7 +278,8 @@ def main():
         "schedule": {"first_level_items": info["coop_items"], "waves_per_workgroup": info["coop_waves"],
                      "redo_items_last": info["redo_items"], "learn_events": info["learn_events"],
                      "dense_separators": info["dense_seps"], "pool_regrows": info["pool_regrows"],
-                     "solve_levels": info["solve_levels"], "solve_order_fallbacks": info["solve_order_fallbacks"]},
+                     "solve_levels": info["solve_levels"], "solve_order_fallbacks": info["solve_order_fallbacks"],
+                     "bin_edge": info["sched_bin_edge"], "autotune_trials": info["autotune_trials"]},
         "solve_kernel_ms": float(np.mean(sk)),
         "scatter_kernel_ms": float(np.mean(sc)),
         "hbm_gbs_factor": achieved,
@@ -281,7 +296,10 @@ def main():
         },
     }
     if args.saturate > 0 and not refactor:
-        out["saturated"] = saturated_leg(bk, torch, a, opts, vals0, B, args.saturate, args.saturate_steps,
+        # the saturated handles use the schedule the autotuner chose for the main handle
+        sat_opts = dict(opts, autotune=0, coop_waves=info["coop_waves"],
+                        bin_edge=info["sched_bin_edge"] if info["sched_bin_edge"] > 0 else -1)
+        out["saturated"] = saturated_leg(bk, torch, a, sat_opts, vals0, B, args.saturate, args.saturate_steps,
                                          bytes_factor, x)
     if not args.no_cpu_baseline:
         import oracle

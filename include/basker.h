@@ -136,6 +136,9 @@ typedef struct {
                                 counts above and sym_ws_rows hold; 0 when the budget ran out */
   int32_t sym_ws_rows;       /* largest column workspace (rows of one column's reach, a separator's
                                 first step included) without row exchanges */
+  int32_t sched_bin_edge;    /* bin edge of the first level's schedule in use (see bin_edge) */
+  int32_t autotune_trials;   /* schedule candidates the autotuner has timed (its choice is in
+                                sched_bin_edge and coop_waves once all are done) */
 } basker_info_t;
 
 /* Fill *o with the defaults listed above. */

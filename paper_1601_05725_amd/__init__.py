@@ -57,7 +57,8 @@ class basker_info_t(ctypes.Structure):
                 ("coop_waves", ctypes.c_int32), ("redo_items", ctypes.c_int32), ("learn_events", ctypes.c_int32),
                 ("solve_order_fallbacks", ctypes.c_int32), ("rows_kernel_ms", ctypes.c_double),
                 ("sym_lnz", ctypes.c_int64), ("sym_unz", ctypes.c_int64), ("fill_bound", ctypes.c_int32),
-                ("sym_ws_rows", ctypes.c_int32)]
+                ("sym_ws_rows", ctypes.c_int32), ("sched_bin_edge", ctypes.c_int32),
+                ("autotune_trials", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}

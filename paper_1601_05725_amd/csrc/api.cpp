@@ -97,6 +97,10 @@ struct basker_ctx {
   bool coop = false;
   int coop_waves = 6;
   int coop_grid = 0;
+  // autotuner: -2 = the first factorization (learning) runs before any trial; 0.. =
+  // index of the next candidate to time; -1 = not tuning
+  int tune_next = -1;
+  std::vector<float> tune_ms;
   // solve tasks, row-wise factors (rebuilt after every factorization), done flags
   DBuf<int32_t> st_kind, st_id, s_status, sflag, LTp, UTp;
   DBuf<int32_t> sfo, sbo, sfo_pos, sbo_pos, row_task0, obad, ocount;   // solve issue orders and their check
@@ -557,6 +561,7 @@ static basker_status make_handle(const basker_options* o, basker_handle* out, ba
     delete h;
     return BASKER_ERR_INVALID;
   }
+  h->tune_next = h->opt.autotune ? -2 : -1;
   h->device = h->opt.device;
   if (h->device < 0) {  // analysis only: no device work
     *ph = h;
@@ -606,6 +611,7 @@ static void fill_info_static(basker_ctx* h) {
   I.device_bytes_plan = plan_device_bytes(P, h->opt);
   I.coop_items = coop_usable(P) ? (int32_t)P.co_item_lo.size() : 0;
   I.coop_waves = coop_waves_of(h->opt);
+  I.sched_bin_edge = bin_edge_of(h->opt);
   I.fill_bound = P.sym_ok ? 1 : 0;
   I.sym_lnz = P.sym_ok ? P.sym_lnz : 0;
   I.sym_unz = P.sym_ok ? P.sym_unz : 0;
@@ -977,7 +983,79 @@ static basker_status learn_deps(basker_ctx* h) {
   return BASKER_OK;
 }
 
+// First-level schedule candidates of the autotuner (bin edge option, wavefronts per
+// workgroup).  Every candidate gives the same factors; only the time differs.
+struct TuneCand {
+  int bin_edge;
+  int waves;
+};
+constexpr TuneCand kTuneCands[] = {{32, 6}, {8, 6}, {128, 6}, {-1, 6}, {32, 8}, {128, 8}, {32, 4}};
+constexpr int kNumTuneCands = (int)(sizeof(kTuneCands) / sizeof(kTuneCands[0]));
+
+// Rebuild the first level's work items for a bin edge and wave count and upload them;
+// the dependency lists stay.  The fallback workspace grows if the wider workgroups need
+// more wavefront regions.
+static basker_status apply_schedule(basker_ctx* h, int bin_edge, int waves) {
+  Plan& P = h->plan;
+  hipStream_t s = h->stream;
+  h->opt.bin_edge = bin_edge;
+  h->opt.coop_waves = waves;
+  build_level0_items(P, h->opt.item_cols ? h->opt.item_cols : 256, bin_edge_of(h->opt));
+  build_issue_order(P);
+  P.co_valid = level0_schedule_valid(P);
+  h->coop = coop_usable(P);
+  h->coop_waves = coop_waves_of(h->opt);
+  h->coop_grid = h->coop ? coop_grid_of(P, h->opt, h->coop_waves) : 0;
+  HIPCHK(h, h->co_item_lo.upload(P.co_item_lo, s));
+  HIPCHK(h, h->co_item_hi.upload(P.co_item_hi, s));
+  HIPCHK(h, h->co_item_cols.upload(P.co_item_cols, s));
+  HIPCHK(h, h->co_item_kind.upload(P.co_item_kind, s));
+  HIPCHK(h, h->col_item.upload(P.col_item, s));
+  HIPCHK(h, h->item_bad.reserve((int64_t)P.co_item_lo.size()));
+  HIPCHK(h, h->co_item_off.upload(P.co_item_off, s));
+  HIPCHK(h, h->co_issue.upload(P.co_issue, s));
+  const int64_t bytes = h->gws_stride * gws_regions(P, h->opt);
+  if (bytes > h->gws.cap) {
+    HIPCHK(h, h->gws.reserve(bytes));
+    HIPCHK(h, hipMemsetAsync(h->gws.p, 0xff, (size_t)bytes, s));
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->info.coop_items = h->coop ? (int32_t)P.co_item_lo.size() : 0;
+  h->info.coop_waves = h->coop_waves;
+  h->info.sched_bin_edge = bin_edge_of(h->opt);
+  return BASKER_OK;
+}
+
+static basker_status do_factor_pass(basker_ctx* h);
+
+// A full factorization; with autotune on, the first ones time the schedule candidates
+// (the first call, which learns dependencies, is not timed) and the fastest is kept.
 static basker_status do_factor(basker_ctx* h) {
+  if (h->tune_next >= 0) {
+    const TuneCand c = kTuneCands[h->tune_next];
+    basker_status r = apply_schedule(h, c.bin_edge, c.waves);
+    if (r != BASKER_OK) return r;
+  }
+  basker_status r = do_factor_pass(h);
+  if (r != BASKER_OK || h->tune_next == -1) return r;
+  if (h->tune_next == -2) {
+    h->tune_next = 0;
+    h->tune_ms.assign(kNumTuneCands, 0.f);
+    return r;
+  }
+  h->tune_ms[h->tune_next] = (float)h->info.factor_kernel_ms;
+  h->info.autotune_trials = ++h->tune_next;
+  if (h->tune_next == kNumTuneCands) {
+    int best = 0;
+    for (int c = 1; c < kNumTuneCands; c++)
+      if (h->tune_ms[c] < h->tune_ms[best]) best = c;
+    h->tune_next = -1;
+    r = apply_schedule(h, kTuneCands[best].bin_edge, kTuneCands[best].waves);
+  }
+  return r;
+}
+
+static basker_status do_factor_pass(basker_ctx* h) {
   drop_refactor_graph(h);   // pools may move
   for (int attempt = 0; attempt < 8; attempt++) {
     int32_t st[ST_WORDS];

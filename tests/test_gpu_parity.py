@@ -546,3 +546,24 @@ def test_one_by_one_block_singular(bk, orc):
         h.factor(a.values)
     assert e.value.status == bk.ERR_NUM_SINGULAR
     assert h.info()["fail_col"] == f.fail_col
+
+
+@pytest.mark.gpu
+def test_autotune_keeps_the_factors(bk, orc):
+    """With autotune on, the first factorizations time the schedule candidates (bin
+    edges, wavefronts per workgroup) and the fastest is kept; every factorization on the
+    way, and the ones after, equal the oracle's bit for bit."""
+    inp = synth.gen_batched_btf(nblocks=500, big=5000, seed=29)
+    a = inp.a
+    h = bk.Handle.symbolic(a, bk.default_options(nd_min_block=2500, nd_leaves=8, autotune=1))
+    prow, qcol, bp, gp = h.ordering()
+    ref = orc.factor(a, orc.Ordering(prow, qcol, bp, gp), update_order=orc.ORDER_ASCENDING)
+    trials = []
+    for call in range(10):
+        h.factor(a.values)
+        inf = h.info()
+        trials.append(inf["autotune_trials"])
+        compare_exact(h.extract(), ref)
+    say("trials %s -> bin edge %d, waves %d" % (trials, inf["sched_bin_edge"], inf["coop_waves"]))
+    assert trials[0] == 0 and trials[-1] == max(trials) >= 6
+    assert inf["coop_waves"] in (4, 6, 8) and inf["sched_bin_edge"] in (0, 8, 32, 128)
