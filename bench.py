@@ -32,6 +32,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
@@ -51,6 +52,13 @@ def make_workload(name):
         inp = synth.gen_batched_btf()
         a = inp.a
         return a, dict(workload="batched_btf_50000_blocks_plus_100k_nd16", n=a.n, nnz=a.nnz,
+                       small_blocks=int(len(inp.block_sizes) - 1), big_block=100000), dict(nd_leaves=16)
+    if name == "c2f":
+        # the batched-BTF configuration's stated order: small power-law blocks are drawn
+        # until n reaches 1,000,000 (the 50,000 blocks of the count alone give n ~ 346k)
+        inp = synth.gen_batched_btf(fill_to=1_000_000)
+        a = inp.a
+        return a, dict(workload="batched_btf_filled_n1000000_plus_100k_nd16", n=a.n, nnz=a.nnz,
                        small_blocks=int(len(inp.block_sizes) - 1), big_block=100000), dict(nd_leaves=16)
     if name == "c3":
         a = synth.gen_mna(500000)
@@ -95,6 +103,48 @@ def committed_traffic(workload):
         return None
 
 
+def factor_flops(ext):
+    """Floating-point operations of the left-looking factorization that produced the
+    factors: every off-diagonal entry U(j, k) applies column j of L to column k (a
+    multiply and a subtract per entry of L(:, j)), and L(:, k) takes one division per
+    entry.  ext: extracted factors (column pointers Lp, Up; U's diagonal last)."""
+    lc = np.diff(np.asarray(ext.Lp, dtype=np.int64))
+    Up = np.asarray(ext.Up, dtype=np.int64)
+    Ui = np.asarray(ext.Ui, dtype=np.int64)
+    offd = np.ones(Ui.size, dtype=bool)
+    offd[Up[1:] - 1] = False
+    return float(2 * lc[Ui[offd]].sum() + lc.sum())
+
+
+def _allcore_worker(a, order, budget_s, start, q):
+    start.wait()
+    rate, reps, el = cpu_baseline(a, order, budget_s)
+    q.put((reps, el))
+
+
+def cpu_baseline_allcore(a, order, budget_s, procs):
+    """The oracle on every host core the run may use: procs child processes (started
+    fresh, not forked from this GPU process), each running the serial factor + solve of
+    the whole workload back to back for about budget_s seconds (independent problems:
+    the CPU's throughput on the same job)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    start = ctx.Event()
+    ps = [ctx.Process(target=_allcore_worker, args=(a, order, budget_s, start, q)) for _ in range(procs)]
+    for p in ps:
+        p.start()
+    time.sleep(2.0)   # let the children import before the clock starts
+    t0 = time.perf_counter()
+    start.set()
+    res = [q.get() for _ in ps]
+    wall = time.perf_counter() - t0
+    for p in ps:
+        p.join()
+    reps = sum(r for r, _ in res)
+    return reps / wall, reps, wall
+
+
 def cpu_baseline(a, order, budget_s, seq=None):
     """The oracle (serial C, one core) on the same matrix and ordering: factor + solve
     repeated until about budget_s seconds are spent.  With a value sequence: one
@@ -131,6 +181,8 @@ def main():
     ap.add_argument("--workload", default=os.environ.get("BASKER_WORKLOAD", "c2"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="processes of the all-core CPU baseline (capped at the usable host CPUs)")
     ap.add_argument("--rate", type=float, default=200.0, help="c4: arrivals per second")
     ap.add_argument("--requests", type=int, default=2000, help="c4: requests in the stream")
     ap.add_argument("--patterns", type=int, default=16, help="c4: distinct patterns")
@@ -246,6 +298,7 @@ def main():
     r = A @ x - b_host
     resid = float(np.abs(r).max() / (abs(A).sum(axis=1).max() * np.abs(x).max() + np.abs(b_host).max()))
 
+    flops = factor_flops(h.extract())
     nnzd, nnzo = info["nnz_diag"], info["nnz_offdiag"]
     lu = info["lnz"] + info["unz"]
     n = a.n
@@ -283,6 +336,8 @@ def main():
         "solve_kernel_ms": float(np.mean(sk)),
         "scatter_kernel_ms": float(np.mean(sc)),
         "hbm_gbs_factor": achieved,
+        "fp64": {"flops_per_factorization": flops, "achieved_gflops": flops / (fk_ms * 1e-3) / 1e9,
+                 "peak_tflops": FP64_PEAK_TFLOPS, "frac": flops / (fk_ms * 1e-3) / (FP64_PEAK_TFLOPS * 1e12)},
         "residual": resid,
         "roofline": {
             "kernel": "factor_kernel (sum of the per-level launches of one factorization)",
@@ -306,9 +361,19 @@ def main():
         prow, qcol, bp, gp = h.ordering()
         order = oracle.Ordering(prow, qcol, bp, gp)
         rate, reps, el = cpu_baseline(a, order, args.cpu_budget, seq=seq_host if refactor else None)
-        out["cpu_baseline"] = {"value": rate, "unit": "factorizations/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d x (%s + solve) of the full workload, %.1f s, serial C oracle" % (
-                                   reps, "refactor" if refactor else "factor", el)}
+        single = {"value": rate, "unit": "factorizations/s", "cores": 1, "kind": "oracle",
+                  "sample": "%d x (%s + solve) of the full workload, %.1f s, serial C oracle" % (
+                      reps, "refactor" if refactor else "factor", el)}
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        procs = max(1, min(ncpu, args.cpu_procs))
+        if procs > 1 and not refactor:
+            arate, areps, awall = cpu_baseline_allcore(a, order, args.cpu_budget, procs)
+            out["cpu_baseline"] = {"value": arate, "unit": "factorizations/s", "cores": procs, "kind": "oracle",
+                                   "sample": "%d processes x serial C oracle, %d x (factor + solve) of the full "
+                                             "workload in %.1f s wall" % (procs, areps, awall),
+                                   "host_cpus_usable": ncpu, "host_cpus": os.cpu_count(), "single_core": single}
+        else:
+            out["cpu_baseline"] = dict(single, host_cpus_usable=ncpu, host_cpus=os.cpu_count())
     h.free()
     print(json.dumps(out), flush=True)
 

@@ -16,7 +16,7 @@ import glob
 import sqlite3
 import sys
 
-FACTOR_KERNELS = ("factor_init_kernel", "factor_kernel", "sepdense_kernel")
+FACTOR_KERNELS = ("factor_init_kernel", "factor_kernel", "factor_coop_kernel", "factor_spec_check_kernel", "sepdense_kernel")
 
 
 def summarize(path):
