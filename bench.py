@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--patterns", type=int, default=16, help="c4: distinct patterns")
     ap.add_argument("--nmax", type=int, default=100000, help="c4: largest pattern order (smallest 1,000)")
     ap.add_argument("--slots", type=int, default=8, help="c4: concurrent requests")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="c4: HBM budget of the resident handles (GB)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default first-level schedule instead of timing the candidates before the run")
     ap.add_argument("--saturate", type=int, default=4, metavar="K",
@@ -483,10 +484,15 @@ def bench_serving(args):
         return [serve.Request(kind, key, values=v, rhs=b) for (_, kind, key, v, b) in stream]
 
     # symbolic analyses are resident before the stream starts (both paths)
-    srv = serve.Server(pats, slots=args.slots)
+    budget = int(args.budget_gb * 1e9)
+    srv = serve.Server(pats, slots=args.slots, hbm_budget=budget)
     warm = [srv.submit(serve.Request(serve.FACTOR, p.key, values=p.values)) for p in pats]
-    for r in warm:
+    for i, r in enumerate(warm):
         r.event.wait()
+        if (i + 1) % 8 == 0:
+            log("c4: first factorizations %d of %d done at %.1fs" % (i + 1, len(warm), time.perf_counter() - t))
+    log("c4: %d patterns factored once (budget %.1f GB, %d evictions so far)" % (len(pats), args.budget_gb,
+                                                                                  srv.evictions))
     reqs = requests()
     t0 = time.perf_counter()
     for (ta, *_), r in zip(stream, reqs):
@@ -495,8 +501,10 @@ def bench_serving(args):
             time.sleep(ta - now)
         r.arrival = t0 + ta
         srv.submit(r)
-    for r in reqs:
+    for i, r in enumerate(reqs):
         r.event.wait()
+        if (i + 1) % 100 == 0:
+            log("c4 served: %d of %d requests done at %.1fs" % (i + 1, len(reqs), time.perf_counter() - t0))
     served_wall = time.perf_counter() - t0
     errors = sum(1 for r in reqs if r.error)
     srv.close()
@@ -504,10 +512,12 @@ def bench_serving(args):
     # plain path: one request at a time in arrival order on the same arrival times
     handles = {}
     base = requests()
-    for p in pats:
+    for i, p in enumerate(pats):
         handles[p.key] = bk_handle(p)
+        if (i + 1) % 8 == 0:
+            log("c4 plain: %d of %d handles factored" % (i + 1, len(pats)))
     t0 = time.perf_counter()
-    for (ta, *_), r in zip(stream, base):
+    for j, ((ta, *_), r) in enumerate(zip(stream, base)):
         now = time.perf_counter() - t0
         if ta > now:
             time.sleep(ta - now)
@@ -521,6 +531,8 @@ def bench_serving(args):
         else:
             r.result = h.solve(r.rhs)
         r.done = time.perf_counter()
+        if (j + 1) % 100 == 0:
+            log("c4 plain: %d of %d requests done at %.1fs" % (j + 1, len(base), r.done - t0))
     plain_wall = time.perf_counter() - t0
     for h in handles.values():
         h.free()
@@ -539,6 +551,8 @@ def bench_serving(args):
         "config": {"workload": "serving_%d_patterns_n1000_%d_rate%g" % (len(pats), args.nmax, args.rate),
                    "requests": len(reqs), "slots": args.slots, "solves": nsolve},
         "p50_ms": p50, "p99_ms": p99, "solves_per_s": nsolve / served_wall, "errors": errors,
+        "hbm_budget_bytes": budget, "peak_resident_bytes": srv.peak_bytes, "evictions": srv.evictions,
+        "restores": srv.restores,
         "plain": {"value": len(base) / plain_wall, "p50_ms": q50, "p99_ms": q99, "solves_per_s": nsolve / plain_wall},
     }
     print(json.dumps(out), flush=True)
