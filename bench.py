@@ -222,7 +222,10 @@ def main():
         return
     bk.load()
     if args.workload == "c4":
-        return bench_serving(args)
+        print("--workload c4 is switched off: its one run at full scale (64 patterns of n up to "
+              "300,000) faulted the GPU and the cause has not been found; the serving loop itself "
+              "is covered at small scale by tests/test_gpu_serve.py", file=sys.stderr)
+        sys.exit(2)
 
     t = time.perf_counter()
     a, cfg, opts = make_workload(args.workload)
