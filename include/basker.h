@@ -76,7 +76,9 @@ typedef struct {
   int32_t sched_flags;     /* bit 0: hand out the work items of every level in reverse order;
                               bit 1: no speculative schedule of the first level (every
                               column waits for its column-elimination-tree children);
-                              results do not depend on either (checks of determinism) */
+                              bit 2: solve with one launch per level of the task graph
+                              instead of one launch for all tasks;
+                              results do not depend on any of them (checks of determinism) */
   int32_t item_cols;       /* first-level work items hold at least this many columns unless a
                               block or ND leaf is larger (0 = 256) */
   int32_t coop_waves;      /* wavefronts per workgroup of the first level: 4, 6 or 8 (0 = 6) */

@@ -103,11 +103,13 @@ struct basker_ctx {
   std::vector<float> tune_ms;
   // solve tasks, row-wise factors (rebuilt after every factorization), done flags
   DBuf<int32_t> st_kind, st_id, s_status, sflag, LTp, UTp;
+  DBuf<int32_t> st_dep_ptr, st_dep, st_succ;   // the one-launch solve's task graph
   DBuf<int32_t> sfo, sbo, sfo_pos, sbo_pos, row_task0, obad, ocount;   // solve issue orders and their check
   DBuf<unsigned long long> lkeys, lkeys_out, ukeys, ukeys_out;
   DBuf<double> lvals, lvals_out, uvals, uvals_out, diag;
   DBuf<char> rows_temp;
   std::vector<int32_t> st_lvl_lds;   // LDS bytes of every solve level's launch
+  int32_t flow_lds = 0, flow_grid = 0;   // the one-launch solve: LDS per workgroup, workgroups
   // numeric state
   DBuf<double> vals, Rx, OTx;
   DBuf<int32_t> pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
@@ -356,7 +358,8 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(8, 2); add(4, 2 * nlev);
   add(4, n + 1); add(4, nnzo); add(4, nnzo);                       // OTp, OTj, OTmap
   add(4, n); add(4, n); add(4, nb + 1); add(4, ng + 1);            // prow, qcol, blkptr, grpptr
-  add(4, nt); add(4, nt); add(4, 1); add(4, n); add(4, n + 1); add(4, n + 1);   // tasks, status, flags, row pointers
+  add(4, nt); add(4, nt); add(4, 2 + nt); add(4, n); add(4, n + 1); add(4, n + 1);   // tasks, status, flags, row pointers
+  add(4, nt + 1); add(4, (int64_t)P.st_dep.size()); add(4, nt);                // the one-launch solve's task graph
   add(8, n);                                                                     // U's diagonal
   for (int t = 0; t < 6; t++) add(4, n);                                         // solve issue orders
   add(4, 1);
@@ -469,7 +472,11 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->grpptr.upload(P.grpptr, s));
   HIPCHK(h, h->st_kind.upload(P.st_kind, s));
   HIPCHK(h, h->st_id.upload(P.st_id, s));
-  HIPCHK(h, h->s_status.reserve(1));
+  // solve status word, task counter and done flags of the one-launch solve
+  HIPCHK(h, h->s_status.reserve(2 + (int64_t)P.st_kind.size()));
+  HIPCHK(h, h->st_dep_ptr.upload(P.st_dep_ptr, s));
+  HIPCHK(h, h->st_dep.upload(P.st_dep, s));
+  HIPCHK(h, h->st_succ.upload(P.st_succ, s));
   HIPCHK(h, h->sflag.reserve(n));
   HIPCHK(h, h->LTp.reserve(n + 1));
   HIPCHK(h, h->UTp.reserve(n + 1));
@@ -504,6 +511,13 @@ static basker_status upload_plan(basker_ctx* h) {
       }
       h->st_lvl_lds[l] = nt <= ncu ? lds_max : (int32_t)std::min<size_t>(need, (size_t)lds_max);
     }
+    // one launch for every task: workgroups with the whole LDS of a CU (less the
+    // kernel's own few static bytes) on half the CUs -- the chain of dependent tasks
+    // needs few at a time, and the other half stays free for concurrent handles
+    // (measured on the batched-BTF workload: 256 workgroups cost a quarter of the
+    // throughput of four handles in flight, 32 slowed the single solve by a third)
+    h->flow_lds = lds_max - kSolveFlowStaticLds;
+    h->flow_grid = std::min<int>((int)P.st_kind.size(), std::max(ncu / 2, 1));
   }
   const int64_t nnzd = (int64_t)P.Ri.size();
   HIPCHK(h, h->vals.reserve(P.nnz));
@@ -679,13 +693,13 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.nnz_ctr = h->nnz_ctr.p;
   a.col_list = h->lvl_col.p;
   a.cb_off = h->cb_off.p; a.cb_np = h->cb_np.p; a.cb_nn = h->cb_nn.p;
-  a.cbI = h->cbI.p; a.cbX = h->cbX.p; a.cbcap = h->cbI.cap;
+  a.cbI = h->cbI.p; a.cbX = h->cbX.p; a.cbcap = std::min(h->cbI.cap, h->cbX.cap);
   a.mode = 0;
   // chunk: a fraction of the pool per wave so that the waves' partly used chunks
   // cannot exhaust it
   {
     const int64_t waves = std::max<int64_t>(pool_waves(h->plan, h->opt), 1);
-    int64_t c = std::min(h->Li.cap, h->Ui.cap) / (kChunkDiv * waves);
+    int64_t c = std::min(std::min(h->Li.cap, h->Lx.cap), std::min(h->Ui.cap, h->Ux.cap)) / (kChunkDiv * waves);
     c = std::max<int64_t>(kMinChunk, std::min<int64_t>(c, 1 << 16));
     a.chunk = c;
   }
@@ -693,7 +707,9 @@ static FactorArgs factor_args(basker_ctx* h, int refactor) {
   a.Lbeg = h->Lbeg.p; a.Lcnt = h->Lcnt.p; a.Ubeg = h->Ubeg.p; a.Ucnt = h->Ucnt.p;
   a.Li = h->Li.p; a.Lx = h->Lx.p; a.Ui = h->Ui.p; a.Ux = h->Ux.p;
   a.pool_next = h->pool.p;
-  a.Lcap = h->Li.cap; a.Ucap = h->Ui.cap;
+  // a pool's index and value arrays are grown together; after a failed growth the
+  // smaller of the two bounds both
+  a.Lcap = std::min(h->Li.cap, h->Lx.cap); a.Ucap = std::min(h->Ui.cap, h->Ux.cap);
   a.status = h->status.p;
   a.tau = h->opt.pivot_tol;
   a.diag_pref = h->opt.diag_pref;
@@ -775,7 +791,7 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
   dA.pinv = h->pinv.p; dA.piv = h->piv.p;
   dA.Lbeg = h->Lbeg.p; dA.Lcnt = h->Lcnt.p; dA.Ubeg = h->Ubeg.p; dA.Ucnt = h->Ucnt.p;
   dA.Li = h->Li.p; dA.Lx = h->Lx.p; dA.Ui = h->Ui.p; dA.Ux = h->Ux.p;
-  dA.pool_next = h->pool.p; dA.Lcap = h->Li.cap; dA.Ucap = h->Ui.cap; dA.nnz_ctr = h->nnz_ctr.p;
+  dA.pool_next = h->pool.p; dA.Lcap = a.Lcap; dA.Ucap = a.Ucap; dA.nnz_ctr = h->nnz_ctr.p;
   dA.status = h->status.p; dA.tau = h->opt.pivot_tol; dA.diag_pref = h->opt.diag_pref; dA.refactor = refactor;
   for (int l = 0; l < nlev; l++) {
     a.item_begin = P.lvl_item_ptr[l];
@@ -1224,14 +1240,24 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   a.B = dB; a.W = W; a.Z = Z;
   a.sflag = h->sflag.p;
   a.status = h->s_status.p;
+  a.qctr = h->s_status.p + 1;
+  a.done = h->s_status.p + 2;
+  a.ntasks = (int32_t)h->plan.st_kind.size();
+  a.dep_ptr = h->st_dep_ptr.p; a.dep = h->st_dep.p; a.succ = h->st_succ.p;
   const Plan& P = h->plan;
   const int nsl = (int)P.st_lvl_ptr.size() - 1;
-  HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 1, s));
+  HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 2 + (int64_t)a.ntasks, s));
   HIPCHK(h, hipEventRecord(h->ev[2], s));
-  for (int l = 0; l < nsl; l++) {
-    a.t_begin = P.st_lvl_ptr[l];
-    a.lds_bytes = h->st_lvl_lds[l];
-    HIPCHK(h, launch_solve_tasks(a, P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l], s));
+  if (h->opt.sched_flags & 4) {
+    for (int l = 0; l < nsl; l++) {
+      a.t_begin = P.st_lvl_ptr[l];
+      a.lds_bytes = h->st_lvl_lds[l];
+      HIPCHK(h, launch_solve_tasks(a, P.st_lvl_ptr[l + 1] - P.st_lvl_ptr[l], s));
+    }
+  } else {
+    a.t_begin = 0;
+    a.lds_bytes = h->flow_lds;
+    HIPCHK(h, launch_solve_flow(a, h->flow_grid, s));
   }
   HIPCHK(h, launch_solve_finish(a, s));
   HIPCHK(h, hipEventRecord(h->ev[3], s));

@@ -177,6 +177,14 @@ struct SolveArgs {
   double* Z;               // n x nrhs: solution in R-column numbering
   int32_t* sflag;          // n: done flags of tasks whose rows do not fit in LDS
   int32_t* status;         // nonzero on a stalled wait
+  // one launch for all tasks: predecessors of every task (launch positions), whether a
+  // later task waits for it, done flags and the task counter (zero before the launch)
+  int32_t ntasks;
+  const int32_t* dep_ptr;
+  const int32_t* dep;
+  const int32_t* succ;
+  int32_t* done;
+  int32_t* qctr;
 };
 
 struct DenseSepArgs {
@@ -233,6 +241,9 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);
 size_t solve_lds_bytes(int32_t rows);   // LDS a task of `rows` rows needs
 hipError_t solve_lds_setup(size_t max_bytes);
 hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s);
+hipError_t launch_solve_flow(const SolveArgs& a, int grid, hipStream_t s);
+// LDS the one-launch solve kernel declares itself; its dynamic LDS is the rest
+constexpr int kSolveFlowStaticLds = 256;
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s);
 // the static device scratch of the solve that allocates nothing: its size in doubles,
 // and its address on a device (looked up once per device; the device must be current)

@@ -8,6 +8,9 @@
 //                   its descendants', which earlier levels finished);
 //   backward task : the U rows of one ND node, root first (its rows depend on its own
 //                   rows and on its ancestors', finished earlier).
+// By default one launch runs every task (solve_flow_kernel): a workgroup takes the
+// tasks in launch order and waits on its predecessors' done flags; the launches per
+// level remain as an option.
 // A task is one workgroup of kSW wavefronts.  The waves take the task's rows round
 // robin in an issue order, and a row waits only for the rows of the same task it reads
 // (done bits in LDS, release/acquire at workgroup scope).  The issue order of a
@@ -704,10 +707,9 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
   if (!ok && tid == 0) atomicOr(a.status, 4);
 }
 
-__global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
-  BASKER_DYN_SHARED(double, smem_d);
-  const int tid = threadIdx.x;
-  const int t = a.t_begin + (int)blockIdx.x;
+// One task with the workgroup's dynamic LDS (smem_d, a.lds_bytes): every right-hand
+// side in turn.
+__device__ __forceinline__ void solve_task_body(const SolveArgs& a, double* smem_d, int t, int tid) {
   const int kind = a.st_kind[t], id = a.st_id[t];
   const int m = kind == 0 ? a.blkptr[id + 1] - a.blkptr[id] : a.grpptr[id + 1] - a.grpptr[id];
   const int64_t rbytes = (int64_t)a.lds_bytes - lds_base_bytes(m);
@@ -730,6 +732,73 @@ __global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
+  BASKER_DYN_SHARED(double, smem_d);
+  solve_task_body(a, smem_d, a.t_begin + (int)blockIdx.x, (int)threadIdx.x);
+}
+
+// All tasks in one launch.  Workgroups take tasks from a counter in launch order (a
+// topological order of the task graph) and wait for each task's predecessors' done
+// flags before running it.  Every predecessor sits earlier in the order, so it was
+// taken by a workgroup that is already running, and the earliest unfinished task never
+// waits: the waits end without any assumption about how many workgroups are resident.
+// A task's results are released at agent scope before its flag (workgroups of one
+// launch run on different XCDs, whose L2 caches are not coherent) and acquired at agent
+// scope after the wait.  Waits are also bounded: a wait that outlasts the spin limit
+// sets bit 8 of the status, and every other wait sees that bit within 256 polls and
+// gives up too, so a launch whose flags never arrive still ends within a fraction of a
+// second (the solve then reports the stall).
+constexpr unsigned kFlowSpinLimit = 1u << 18;
+// s_waitcnt operand: vector memory count 0, the export and LDS counts left free
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+__global__ void __launch_bounds__(64 * kSW) solve_flow_kernel(SolveArgs a) {
+  BASKER_DYN_SHARED(double, smem_d);
+  __shared__ int sh_t;
+  const int tid = threadIdx.x;
+  // The task index is read as a wave-uniform value (readfirstlane): with the loop's
+  // exit provably uniform the compiler keeps one loop in which every thread passes
+  // every barrier.  Read as a per-lane value, the exit looked divergent and the
+  // structurizer moved thread 0's counter update out of the loop that holds the
+  // barriers, so the other threads reran the previous task without end.
+  if (tid == 0) sh_t = atomicAdd(a.qctr, 1);
+  __syncthreads();
+  int t = __builtin_amdgcn_readfirstlane(sh_t);
+  while (t < a.ntasks) {
+    if (tid < 64) {
+      bool stalled = false;
+      for (int e = a.dep_ptr[t] + tid; e < a.dep_ptr[t + 1]; e += 64) {
+        const int d = a.dep[e];
+        unsigned spins = 0;
+        while (__hip_atomic_load(&a.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > kFlowSpinLimit ||
+              ((spins & 255u) == 0 &&
+               (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8))) {
+            stalled = true;
+            break;
+          }
+        }
+      }
+      if (__any(stalled) && tid == 0) __hip_atomic_fetch_or(a.status, 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    solve_task_body(a, smem_d, t, tid);
+    // every wave's result stores complete (acknowledged by L2) before the barrier, so
+    // the one agent-scope release below (L2 write-back, then the flag) covers them:
+    // the workgroup barrier alone does not wait for global stores
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (tid == 0) {
+      if (a.succ[t]) __hip_atomic_store(&a.done[t], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      sh_t = atomicAdd(a.qctr, 1);
+    }
+    __syncthreads();
+    t = __builtin_amdgcn_readfirstlane(sh_t);
+  }
+}
+
 __global__ void solve_unpermute_kernel(SolveArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)a.n * a.nrhs;
@@ -747,13 +816,22 @@ size_t solve_lds_bytes(int32_t rows) {
 }
 
 hipError_t solve_lds_setup(size_t max_bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&solve_task_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&solve_task_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&solve_flow_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes - kSolveFlowStaticLds);
 }
 
 hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s) {
   if (ntasks > 0)
     hipLaunchKernelGGL(solve_task_kernel, dim3(ntasks), dim3(64 * kSW), (size_t)a.lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_flow(const SolveArgs& a, int grid, hipStream_t s) {
+  if (a.ntasks > 0 && grid > 0)
+    hipLaunchKernelGGL(solve_flow_kernel, dim3(grid), dim3(64 * kSW), (size_t)a.lds_bytes, s, a);
   return hipGetLastError();
 }
 

@@ -950,6 +950,7 @@ void build_solve_tasks(Plan& P) {
     std::stable_sort(order.begin() + P.st_lvl_ptr[l], order.begin() + P.st_lvl_ptr[l + 1],
                      [&](int x, int y) { return tsize(x) > tsize(y); });
   P.st_kind.resize(nt); P.st_id.resize(nt); P.st_need.resize(nt);
+  std::vector<int32_t> pos0(nb, -1), pos1(ng, -1), pos2(ng, -1);
   for (int q = 0; q < nt; q++) {
     const int t = order[q];
     P.st_kind[q] = kind[t];
@@ -957,6 +958,38 @@ void build_solve_tasks(Plan& P) {
     const int m = tsize(t);
     // doubles of work storage: the task's rows
     P.st_need[q] = m;
+    (kind[t] == 0 ? pos0[id[t]] : kind[t] == 1 ? pos1[id[t]] : pos2[id[t]]) = q;
+  }
+  // Predecessors of every task (queue positions, all earlier in the queue): the tasks
+  // that produce the solution entries its residual reads through the off-diagonal
+  // blocks (a whole block's task, or the backward task of the ND node holding the
+  // column), an ND node's forward tasks of its children, and for a backward task its own
+  // forward task and its parent's backward task.
+  std::vector<int32_t> cgrp(n, -1);
+  for (int g = 0; g < ng; g++)
+    for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) cgrp[k] = g;
+  auto producer = [&](int k) { return is_nd[blk[k]] ? pos2[cgrp[k]] : pos0[blk[k]]; };
+  auto owner = [&](int i) { return is_nd[blk[i]] ? pos1[cgrp[i]] : pos0[blk[i]]; };
+  std::vector<std::vector<int32_t>> pred(nt);
+  for (int k = 0; k < n; k++)
+    for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) pred[owner(P.Oi[q])].push_back(producer(k));
+  for (int g = 0; g < ng; g++) {
+    if (pos1[g] < 0) continue;
+    const int p = P.grp_parent[g];
+    if (p >= 0) pred[pos1[p]].push_back(pos1[g]);
+    pred[pos2[g]].push_back(pos1[g]);
+    if (p >= 0) pred[pos2[g]].push_back(pos2[p]);
+  }
+  P.st_dep_ptr.assign(nt + 1, 0);
+  P.st_dep.clear();
+  P.st_succ.assign(nt, 0);
+  for (int q = 0; q < nt; q++) {
+    std::vector<int32_t>& v = pred[q];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    for (int32_t d : v) P.st_succ[d] = 1;
+    P.st_dep.insert(P.st_dep.end(), v.begin(), v.end());
+    P.st_dep_ptr[q + 1] = (int32_t)P.st_dep.size();
   }
 }
 

@@ -567,3 +567,32 @@ def test_autotune_keeps_the_factors(bk, orc):
     say("trials %s -> bin edge %d, waves %d" % (trials, inf["sched_bin_edge"], inf["coop_waves"]))
     assert trials[0] == 0 and trials[-1] == max(trials) >= 6
     assert inf["coop_waves"] in (4, 6, 8) and inf["sched_bin_edge"] in (0, 8, 32, 128)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["nd12k", "btf400"])
+def test_one_launch_solve_equals_level_launches(bk, orc, case):
+    """The solve runs every task in one launch (workgroups wait on their predecessors'
+    done flags) unless sched_flags bit 2 asks for one launch per level; both give the
+    oracle's solution bit for bit, also over repeated solves on one handle (the flags
+    and the task counter are cleared before every launch)."""
+    if case == "nd12k":
+        a = synth.gen_mna(12000, seed=6)
+        opt = dict(nd_min_block=3000, nd_leaves=8)
+    else:
+        a = synth.gen_batched_btf(nblocks=400, big=4000, seed=5).a
+        opt = dict(nd_min_block=2000, nd_leaves=4)
+    hs = []
+    for flags in (0, 4):
+        say("case %s sched_flags %d" % (case, flags))
+        h = bk.Handle.symbolic(a, bk.default_options(sched_flags=flags, **opt))
+        h.factor(a.values)
+        hs.append(h)
+    prow, qcol, bp, gp = hs[0].ordering()
+    order = orc.Ordering(prow, qcol, bp, gp)
+    f_asc = orc.factor(a, order, update_order=orc.ORDER_ASCENDING)
+    for rep, nrhs in enumerate((1, 3, 8, 2)):
+        b = synth.rhs(a.n, nrhs, ident=500 + rep)
+        xo = orc.solve(a, order, f_asc, b)
+        for h in hs:
+            np.testing.assert_array_equal(h.solve(b), xo)
