@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c4: HBM budget of the resident handles (GB)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default first-level schedule instead of timing the candidates before the run")
+    ap.add_argument("--schedule", default="", metavar="BIN,WAVES",
+                    help="fixed first-level schedule (bin edge, wavefronts per workgroup) instead of the "
+                         "autotuner's pick, e.g. 128,8 (for counter runs that must repeat one schedule)")
     ap.add_argument("--saturate", type=int, default=4, metavar="K",
                     help="saturated leg: K handles of the workload, each factor+solve loop in its own host "
                          "thread on one of min(K, 4) streams (0: skip)")
@@ -231,6 +234,10 @@ def main():
     a, cfg, opts = make_workload(args.workload)
     log("workload %s n=%d nnz=%d generated in %.1fs" % (cfg["workload"], a.n, a.nnz, time.perf_counter() - t))
     t = time.perf_counter()
+    if args.schedule:
+        be, wv = (int(x) for x in args.schedule.split(","))
+        opts = dict(opts, bin_edge=be, coop_waves=wv)
+        args.no_autotune = True
     if not args.no_autotune:
         opts = dict(opts, autotune=1)
     h = bk.Handle.symbolic(a, bk.default_options(**opts))
