@@ -744,11 +744,13 @@ __global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
 // waits: the waits end without any assumption about how many workgroups are resident.
 // A task's results are released at agent scope before its flag (workgroups of one
 // launch run on different XCDs, whose L2 caches are not coherent) and acquired at agent
-// scope after the wait.  Waits are also bounded: a wait that outlasts the spin limit
-// sets bit 8 of the status, and every other wait sees that bit within 256 polls and
-// gives up too, so a launch whose flags never arrive still ends within a fraction of a
-// second (the solve then reports the stall).
-constexpr unsigned kFlowSpinLimit = 1u << 18;
+// scope after the wait.  Waits are also bounded, by elapsed time (the 100 MHz real-time
+// counter), not by a poll count: a predecessor can legitimately run for tens of
+// milliseconds (the root separator of a 500k-row circuit does).  A wait that outlasts
+// the bound sets bit 8 of the status, and every other wait sees that bit within 256
+// polls and gives up too, so a launch whose flags never arrive still ends (the solve
+// then reports the stall).
+constexpr unsigned long long kFlowWaitTicks = 1000000000ull;   // 10 s at 100 MHz
 // s_waitcnt operand: vector memory count 0, the export and LDS counts left free
 constexpr int kWaitVmcnt0 = 0x0F70;
 
@@ -770,10 +772,11 @@ __global__ void __launch_bounds__(64 * kSW) solve_flow_kernel(SolveArgs a) {
       for (int e = a.dep_ptr[t] + tid; e < a.dep_ptr[t + 1]; e += 64) {
         const int d = a.dep[e];
         unsigned spins = 0;
+        const unsigned long long w0 = __builtin_amdgcn_s_memrealtime();
         while (__hip_atomic_load(&a.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
           __builtin_amdgcn_s_sleep(2);
-          if (++spins > kFlowSpinLimit ||
-              ((spins & 255u) == 0 &&
+          if ((++spins & 255u) == 0 &&
+              (__builtin_amdgcn_s_memrealtime() - w0 > kFlowWaitTicks ||
                (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8))) {
             stalled = true;
             break;
