@@ -89,7 +89,7 @@ struct basker_ctx {
   DBuf<int32_t> dsep_seg, dsep_H, dsep_rng_ptr, dsep_rng_g0, dsep_rng_len, dsep_rng_loc, piv_local;
   DBuf<int64_t> dsep_poff, dsep_soff;
   DBuf<double> dpanel;
-  DBuf<unsigned long long> dbits;
+  DBuf<unsigned long long> dbits, dscratch;
   DBuf<int32_t> OTp, OTj, OTmap, prow, qcol, blkptr, grpptr;
   // first-level cooperative schedule
   DBuf<int32_t> co_item_lo, co_item_hi, co_item_cols, col_item, dep_ptr, dep_idx, sdep_ptr, sdep_idx, item_bad;
@@ -352,6 +352,7 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(4, nd); add(4, nd); add(4, nd + 1); add(4, nr); add(4, nr); add(4, nr);
   add(8, nd); add(8, nd);
   add(8, P.dsep_panel_total); add(8, P.dsep_bits_total);
+  add(8, (int64_t)kMaxPanelWords * (1 + kMaxNb));
   add(4, n); add(4, n); add(4, n); add(4, n);                      // piv_local, cb_off/np/nn
   const int64_t cb = cb_capacity(P);
   add(4, cb); add(8, cb);
@@ -455,6 +456,9 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->dsep_soff.upload(P.dsep_soff, s));
   HIPCHK(h, h->dpanel.reserve(std::max<int64_t>(P.dsep_panel_total, 1)));
   HIPCHK(h, h->dbits.reserve(std::max<int64_t>(P.dsep_bits_total, 1)));
+  // pivotal set and block L structure handed between the launches of a separator factored
+  // block by block
+  HIPCHK(h, h->dscratch.reserve((int64_t)kMaxPanelWords * (1 + kMaxNb)));
   HIPCHK(h, h->piv_local.reserve(n));
   HIPCHK(h, h->cb_off.reserve(n));
   HIPCHK(h, h->cb_np.reserve(n));
@@ -793,6 +797,7 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
   dA.Li = h->Li.p; dA.Lx = h->Lx.p; dA.Ui = h->Ui.p; dA.Ux = h->Ux.p;
   dA.pool_next = h->pool.p; dA.Lcap = a.Lcap; dA.Ucap = a.Ucap; dA.nnz_ctr = h->nnz_ctr.p;
   dA.status = h->status.p; dA.tau = h->opt.pivot_tol; dA.diag_pref = h->opt.diag_pref; dA.refactor = refactor;
+  dA.pbits_g = h->dscratch.p; dA.lb_g = h->dscratch.p + kMaxPanelWords;
   for (int l = 0; l < nlev; l++) {
     a.item_begin = P.lvl_item_ptr[l];
     a.item_end = P.lvl_item_ptr[l + 1];
@@ -864,6 +869,13 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     }
     dA.d_begin = P.lvl_dsep_ptr[l];
     if ((e = launch_sepdense(dA, P.lvl_dsep_ptr[l + 1] - P.lvl_dsep_ptr[l], s)) != hipSuccess) return e;
+    // separators of several blocks (the launch above skips them): block by block
+    for (int d = P.lvl_dsep_ptr[l]; d < P.lvl_dsep_ptr[l + 1]; d++) {
+      const int sg = P.dsep_seg[d], H = P.dsep_H[d], m = P.seg_c1[sg] - P.seg_c0[sg];
+      if (sep_split(m, block_width(H, (H + 63) / 64, m, kSepDenseLds)) &&
+          (e = launch_sepdense_split(dA, d, H, m, kNumCu, s)) != hipSuccess)
+        return e;
+    }
     if ((e = trace_level_done(h, l, "separator")) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -218,14 +218,39 @@ struct DenseSepArgs {
   double tau;
   int32_t diag_pref;
   int32_t refactor;
+  // separators factored block by block: the pivotal set (kMaxPanelWords words) and the
+  // current block's L structure (W x nb words), carried from launch to launch
+  unsigned long long* pbits_g;
+  unsigned long long* lb_g;
 };
 
 // dense separators: panel rows up to 64 * kMaxPanelWords (one LDS row bitmask), an LDS
 // block of kSepDenseLds bytes (set once per process with sepdense_setup)
 constexpr int kMaxPanelWords = 176;
+constexpr int kMaxNb = 32;          // dense block width
+// Rows whose block-column L memberships are kept as one 32-bit mask each (the trailing
+// update then visits only the block columns that update a row).
+constexpr int kRowMaskRows = 4096;
+
+// dense block width for panel height H: the LDS block holds nb columns of H doubles and
+// two bitmasks of W words each, after the row masks (H words when H <= kRowMaskRows)
+__host__ __device__ inline int block_width(int H, int W, int m, int lds_bytes) {
+  if (H <= kRowMaskRows) lds_bytes -= 4 * H;
+  int nb = lds_bytes / (8 * H + 16 * W);
+  if (nb > kMaxNb) nb = kMaxNb;
+  if (nb > m) nb = m;
+  return nb < 1 ? 1 : nb;
+}
+
+// a separator of at least this many blocks is factored block by block in separate
+// launches, its trailing updates spread over many workgroups
+constexpr int kSplitBlocks = 3;
+__host__ __device__ inline bool sep_split(int m, int nb) { return (m + nb - 1) / nb >= kSplitBlocks; }
 constexpr int kSepDenseLds = 128 * 1024;
 hipError_t sepdense_setup();
 hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s);
+// one separator (sep_split) block by block; ncu = workgroups for the spread launches
+hipError_t launch_sepdense_split(const DenseSepArgs& a, int d, int H, int m, int ncu, hipStream_t s);
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
 // first level on workgroups of `waves` wavefronts (4, 6 or 8); grid workgroups

@@ -29,6 +29,8 @@
 // that updates it), so the stored L and U patterns are exactly the sparse ones.
 #include "device.hpp"
 
+#include <algorithm>
+
 namespace basker {
 
 namespace {
@@ -36,7 +38,6 @@ namespace {
 constexpr int kDT = 1024;             // threads per workgroup
 constexpr int kNW = kDT / 64;
 constexpr int kMaxPivl = 4096;        // local pivots kept in LDS for separators up to this size
-constexpr int kMaxNb = 32;            // block width
 
 __device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
@@ -73,105 +74,142 @@ __device__ __forceinline__ int32_t global_row(const Ranges& rg, int loc) {
 
 __device__ __forceinline__ bool bit(const unsigned long long* b, int i) { return (b[i >> 6] >> (i & 63)) & 1ull; }
 
-// Rows whose block-column L memberships are kept as one 32-bit mask each (the trailing
-// update then visits only the block columns that update a row).
-constexpr int kRowMaskRows = 4096;
 
-// block width for panel height H: the LDS block holds nb columns of H doubles and two
-// bitmasks of W words each, after the row masks (H words when H <= kRowMaskRows)
-__device__ __forceinline__ int block_width(int H, int W, int m, int lds_bytes) {
-  if (H <= kRowMaskRows) lds_bytes -= 4 * H;
-  int nb = lds_bytes / (8 * H + 16 * W);
-  if (nb > kMaxNb) nb = kMaxNb;
-  if (nb > m) nb = m;
-  return nb < 1 ? 1 : nb;
-}
+// LDS the dense kernels declare besides the block area
+struct SepShared {
+  unsigned long long piv_bits[kMaxPanelWords]; // rows already pivotal
+  int pivl_s[kMaxPivl];                        // local pivot rows (m <= kMaxPivl, whole-separator role)
+  double ush[kNW][kMaxNb];                     // per wave: u_t of its trailing column
+  double red_v[kNW];
+  int red_i[kNW];
+  int sh_fail;
+  Ranges rg;
+};
 
-__global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a, int lds_bytes) {
-  extern __shared__ double blk[];                         // H x nb values, then the bitmasks
-  __shared__ unsigned long long piv_bits[kMaxPanelWords]; // rows already pivotal
-  __shared__ int pivl_s[kMaxPivl];                        // local pivot rows (m <= kMaxPivl)
-  __shared__ double ush[kNW][kMaxNb];                     // per wave: u_t of its trailing column
-  __shared__ double red_v[kNW];
-  __shared__ int red_i[kNW];
-  __shared__ int sh_fail;
-  __shared__ Ranges rg;
-
+// Roles: 0 = a whole separator in one workgroup (separators of a few blocks); for the
+// others (sep_split) the host runs 1 = zero the panel and scatter the partial columns
+// (columns spread over the workgroups), then per block 2 = factor the block and write its
+// columns (one workgroup), 3 = bring the later columns up to date with the block (the
+// columns spread over the workgroups).  The arithmetic of every entry, and its order, is
+// the same in every role.
+template <int kRole>
+__device__ __forceinline__ void sep_run(const DenseSepArgs& a, int d, int lds_bytes, int k0_arg, double* blk,
+                                        SepShared& sh) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int d = a.d_begin + blockIdx.x;
   const int sg = a.dsep_seg[d];
   const int c0 = a.seg_c0[sg];
   const int m = a.seg_c1[sg] - c0;
   const int H = a.dsep_H[d];
   const int W = (H + 63) / 64;
+  const int nb = block_width(H, W, m, lds_bytes);
+  if (kRole == 0 && sep_split(m, nb)) return;
+  if (kRole != 0 && __hip_atomic_load(&a.status[ST_CODE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != DEV_OK)
+    return;   // the factorization has failed: nothing more to do (uniform)
   double* P = a.panel + a.poff[d];
   unsigned long long* S = a.bits + a.soff[d];
   int32_t* pivl = a.piv_local + c0;   // local pivot row of each separator column
-  const bool pl_lds = m <= kMaxPivl;
-  const int nb = block_width(H, W, m, lds_bytes);
+  const bool pl_lds = kRole == 0 && m <= kMaxPivl;
   const bool use_rm = H <= kRowMaskRows;
   double* Pb = blk;                                                                       // H x nb
   unsigned long long* Sb = reinterpret_cast<unsigned long long*>(blk + (size_t)H * nb);   // W x nb structure
   unsigned long long* Lb = Sb + (size_t)W * nb;                                           // W x nb L structure
   unsigned* rmask = reinterpret_cast<unsigned*>(Lb + (size_t)W * nb);                     // H row masks
+  unsigned long long* piv_bits = sh.piv_bits;
+  int* pivl_s = sh.pivl_s;
+  double (*ush)[kMaxNb] = sh.ush;
+  double* red_v = sh.red_v;
+  int* red_i = sh.red_i;
+  int& sh_fail = sh.sh_fail;
+  Ranges& rg = sh.rg;
 
-  // zero the panel, clear the pivotal set, ranges into LDS
-  for (int64_t i = tid; i < (int64_t)H * m; i += kDT) P[i] = 0.0;
-  for (int i = tid; i < kMaxPanelWords; i += kDT) piv_bits[i] = 0ull;
-  if (tid == 0) {
-    sh_fail = 0;
-    const int r0 = a.rng_ptr[d], nr = a.rng_ptr[d + 1] - r0;
-    rg.n = nr;
-    if (nr > kMaxRanges) sh_fail = 1;
-    for (int t = 0; t < nr && t < kMaxRanges; t++) {
-      rg.g0[t] = a.rng_g0[r0 + t];
-      rg.loc[t] = a.rng_loc[r0 + t];
-      rg.len[t] = a.rng_len[r0 + t];
+  // ranges into LDS (the trailing role does not map rows)
+  if (kRole != 3) {
+    if (tid == 0) {
+      sh_fail = 0;
+      const int r0 = a.rng_ptr[d], nr = a.rng_ptr[d + 1] - r0;
+      rg.n = nr;
+      if (nr > kMaxRanges) sh_fail = 1;
+      for (int t = 0; t < nr && t < kMaxRanges; t++) {
+        rg.g0[t] = a.rng_g0[r0 + t];
+        rg.loc[t] = a.rng_loc[r0 + t];
+        rg.len[t] = a.rng_len[r0 + t];
+      }
+    }
+    __syncthreads();
+    if (sh_fail) {
+      if (tid == 0) { atomicMax(&a.status[ST_CODE], DEV_PATTERN); atomicMin(&a.status[ST_FAILCOL], c0); }
+      return;
     }
   }
-  __syncthreads();
-  if (sh_fail) {
-    if (tid == 0) { atomicMax(&a.status[ST_CODE], DEV_PATTERN); atomicMin(&a.status[ST_FAILCOL], c0); }
-    return;
-  }
-  // the partial columns from the first step: non-pivotal rows with their values; the
-  // structure words of a column are gathered in the wave's part of the (still unused)
-  // block area with LDS atomics, then stored whole
-  for (int k = wv; k < m; k += kNW) {
-    unsigned long long* sw = Sb + (size_t)wv * W;
-    for (int w = lane; w < W; w += 64) sw[w] = 0ull;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const int c = c0 + k;
-    const int off = a.cb_off[c] + a.cb_np[c], nn = a.cb_nn[c];
-    for (int t = lane; t < nn; t += 64) {
-      const int loc = local_row(rg, a.cbI[off + t]);
-      if (loc < 0) { sh_fail = 1; continue; }
-      P[loc + (int64_t)k * H] = a.cbX[off + t];
-      atomicOr(&sw[loc >> 6], 1ull << (loc & 63));
+  if (kRole == 0 || kRole == 1) {
+    // zero the panel (role 0: all of it first; role 1: each column by the wave that
+    // scatters into it, just before)
+    if (kRole == 0) {
+      for (int64_t i = tid; i < (int64_t)H * m; i += kDT) P[i] = 0.0;
+      __syncthreads();
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int w = lane; w < W; w += 64) S[(int64_t)k * W + w] = sw[w];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    // the partial columns from the first step: non-pivotal rows with their values; the
+    // structure words of a column are gathered in the wave's part of the (still unused)
+    // block area with LDS atomics, then stored whole
+    const int kfirst = (kRole == 0 ? 0 : (int)blockIdx.x * kNW) + wv;
+    const int kstep = (kRole == 0 ? 1 : (int)gridDim.x) * kNW;
+    for (int k = kfirst; k < m; k += kstep) {
+      unsigned long long* sw = Sb + (size_t)wv * W;
+      for (int w = lane; w < W; w += 64) sw[w] = 0ull;
+      if (kRole == 1) {
+        for (int i = lane; i < H; i += 64) P[i + (int64_t)k * H] = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int c = c0 + k;
+      const int off = a.cb_off[c] + a.cb_np[c], nn = a.cb_nn[c];
+      for (int t = lane; t < nn; t += 64) {
+        const int loc = local_row(rg, a.cbI[off + t]);
+        if (loc < 0) { sh_fail = 1; continue; }
+        P[loc + (int64_t)k * H] = a.cbX[off + t];
+        atomicOr(&sw[loc >> 6], 1ull << (loc & 63));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int w = lane; w < W; w += 64) S[(int64_t)k * W + w] = sw[w];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (sh_fail) {
+      if (tid == 0) { atomicMax(&a.status[ST_CODE], DEV_PATTERN); atomicMin(&a.status[ST_FAILCOL], c0); }
+      return;
+    }
+    if (kRole == 1) {
+      // the pivotal set the block role carries from block to block starts empty
+      if (blockIdx.x == 0)
+        for (int i = tid; i < kMaxPanelWords; i += kDT) a.pbits_g[i] = 0ull;
+      return;
+    }
   }
+  if (kRole == 0)
+    for (int i = tid; i < kMaxPanelWords; i += kDT) piv_bits[i] = 0ull;
+  if (kRole == 2)
+    for (int i = tid; i < kMaxPanelWords; i += kDT) piv_bits[i] = a.pbits_g[i];
+  // trailing columns of this workgroup
+  const int tfirst = (kRole == 3 ? (int)blockIdx.x * kNW : 0) + wv;
+  const int tstep = (kRole == 3 ? (int)gridDim.x : 1) * kNW;
   __syncthreads();
-  if (sh_fail) {
-    if (tid == 0) { atomicMax(&a.status[ST_CODE], DEV_PATTERN); atomicMin(&a.status[ST_FAILCOL], c0); }
-    return;
-  }
 
   long long lnz = 0, unz = 0;
   int offdiag = 0;
-  for (int k0 = 0; k0 < m; k0 += nb) {
+  const int kb0 = kRole == 0 ? 0 : k0_arg;
+  const int kb1 = kRole == 0 ? m : (k0_arg + 1 < m ? k0_arg + 1 : m);
+  for (int k0 = kb0; k0 < kb1; k0 += nb) {
     const int nbk = (m - k0 < nb) ? m - k0 : nb;
-    // ---- load the block (its columns have every update from earlier blocks)
-    for (int64_t i = tid; i < (int64_t)H * nbk; i += kDT) Pb[i] = P[i + (int64_t)k0 * H];
-    for (int i = tid; i < W * nbk; i += kDT) Sb[i] = S[i + (int64_t)k0 * W];
-    __syncthreads();
+    if (kRole != 3) {
+      // ---- load the block (its columns have every update from earlier blocks)
+      for (int64_t i = tid; i < (int64_t)H * nbk; i += kDT) Pb[i] = P[i + (int64_t)k0 * H];
+      for (int i = tid; i < W * nbk; i += kDT) Sb[i] = S[i + (int64_t)k0 * W];
+      __syncthreads();
     // ---- factor the block column by column
     for (int t = 0; t < nbk; t++) {
       const int k = k0 + t;
@@ -353,6 +391,20 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a, int lds_b
       }
       if (p != k) offdiag++;
     }
+    } else {
+      // the block as the block role left it: factored values and L structure
+      for (int64_t i = tid; i < (int64_t)H * nbk; i += kDT) Pb[i] = P[i + (int64_t)k0 * H];
+      for (int i = tid; i < W * nbk; i += kDT) Lb[i] = a.lb_g[i];
+      __syncthreads();
+    }
+    if (kRole == 2) {
+      // hand the block to the trailing role: its values, L structure and the pivotal set
+      __syncthreads();
+      for (int64_t i = tid; i < (int64_t)H * nbk; i += kDT) P[i + (int64_t)k0 * H] = Pb[i];
+      for (int i = tid; i < W * nbk; i += kDT) a.lb_g[i] = Lb[i];
+      for (int i = tid; i < kMaxPanelWords; i += kDT) a.pbits_g[i] = piv_bits[i];
+    }
+    if (kRole == 0 || kRole == 3) {
     // ---- bring every later column up to date with the block, one wave a column
     if (k0 + nbk < m) {
       if (use_rm) {
@@ -365,7 +417,7 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a, int lds_b
         __syncthreads();
       }
       const int p_l = lane < nbk ? (pl_lds ? pivl_s[k0 + lane] : pivl[k0 + lane]) : 0;
-      for (int cc = k0 + nbk + wv; cc < m; cc += kNW) {
+      for (int cc = k0 + nbk + tfirst; cc < m; cc += tstep) {
         double* Pc = P + (int64_t)cc * H;
         unsigned long long* Scol = S + (int64_t)cc * W;
         // lane t < nbk: the column's entry in pivot row p_t and whether it is structural
@@ -423,29 +475,86 @@ __global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a, int lds_b
         __builtin_amdgcn_wave_barrier();
       }
     }
+    }
     __syncthreads();
   }
-  if (tid == 0) atomicAdd(&a.status[ST_DSEP], 1);
-  if (lane == 0) {
-    if (offdiag) atomicAdd(&a.status[ST_OFFDIAG], offdiag);
-    if (!a.refactor && (lnz || unz)) {
-      atomicAdd(&a.nnz_ctr[0], (unsigned long long)lnz);
-      atomicAdd(&a.nnz_ctr[1], (unsigned long long)unz);
+  if (kRole == 0 || (kRole == 2 && k0_arg + nb >= m))
+    if (tid == 0) atomicAdd(&a.status[ST_DSEP], 1);
+  if (kRole == 0 || kRole == 2) {
+    if (lane == 0) {
+      if (offdiag) atomicAdd(&a.status[ST_OFFDIAG], offdiag);
+      if (!a.refactor && (lnz || unz)) {
+        atomicAdd(&a.nnz_ctr[0], (unsigned long long)lnz);
+        atomicAdd(&a.nnz_ctr[1], (unsigned long long)unz);
+      }
     }
   }
+}
+
+__global__ void __launch_bounds__(kDT) sepdense_kernel(DenseSepArgs a, int lds_bytes) {
+  BASKER_DYN_SHARED(double, blk);
+  BASKER_SHARED(SepShared, sh);
+  sep_run<0>(a, a.d_begin + (int)blockIdx.x, lds_bytes, 0, blk, sh);
+}
+
+__global__ void __launch_bounds__(kDT) sepdense_prep_kernel(DenseSepArgs a, int lds_bytes) {
+  BASKER_DYN_SHARED(double, blk);
+  BASKER_SHARED(SepShared, sh);
+  sep_run<1>(a, a.d_begin, lds_bytes, 0, blk, sh);
+}
+
+__global__ void __launch_bounds__(kDT) sepdense_block_kernel(DenseSepArgs a, int lds_bytes, int k0) {
+  BASKER_DYN_SHARED(double, blk);
+  BASKER_SHARED(SepShared, sh);
+  sep_run<2>(a, a.d_begin, lds_bytes, k0, blk, sh);
+}
+
+__global__ void __launch_bounds__(kDT) sepdense_trail_kernel(DenseSepArgs a, int lds_bytes, int k0) {
+  BASKER_DYN_SHARED(double, blk);
+  BASKER_SHARED(SepShared, sh);
+  sep_run<3>(a, a.d_begin, lds_bytes, k0, blk, sh);
 }
 
 }  // namespace
 
 hipError_t sepdense_setup() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&sepdense_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, kSepDenseLds);
+  const void* ks[4] = {reinterpret_cast<const void*>(&sepdense_kernel),
+                       reinterpret_cast<const void*>(&sepdense_prep_kernel),
+                       reinterpret_cast<const void*>(&sepdense_block_kernel),
+                       reinterpret_cast<const void*>(&sepdense_trail_kernel)};
+  for (const void* k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kSepDenseLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s) {
   if (nsep <= 0) return hipSuccess;
   hipLaunchKernelGGL(sepdense_kernel, dim3(nsep), dim3(kDT), kSepDenseLds, s, a, kSepDenseLds);
   return hipGetLastError();
+}
+
+hipError_t launch_sepdense_split(const DenseSepArgs& a0, int d, int H, int m, int ncu, hipStream_t s) {
+  DenseSepArgs a = a0;
+  a.d_begin = d;
+  const int W = (H + 63) / 64;
+  const int nb = block_width(H, W, m, kSepDenseLds);
+  hipError_t e;
+  const int gp = std::max(1, std::min((m + kNW - 1) / kNW, ncu));
+  hipLaunchKernelGGL(sepdense_prep_kernel, dim3(gp), dim3(kDT), kSepDenseLds, s, a, kSepDenseLds);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k0 = 0; k0 < m; k0 += nb) {
+    hipLaunchKernelGGL(sepdense_block_kernel, dim3(1), dim3(kDT), kSepDenseLds, s, a, kSepDenseLds, k0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int rest = m - k0 - nb;
+    if (rest > 0) {
+      const int gt = std::max(1, std::min((rest + kNW - 1) / kNW, ncu));
+      hipLaunchKernelGGL(sepdense_trail_kernel, dim3(gt), dim3(kDT), kSepDenseLds, s, a, kSepDenseLds, k0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace basker
