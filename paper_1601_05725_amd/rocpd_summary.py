@@ -16,7 +16,8 @@ import glob
 import sqlite3
 import sys
 
-FACTOR_KERNELS = ("factor_init_kernel", "factor_kernel", "factor_coop_kernel", "factor_spec_check_kernel", "sepdense_kernel")
+FACTOR_KERNELS = ("factor_init_kernel", "factor_kernel", "factor_coop_kernel", "factor_spec_check_kernel",
+                  "sepdense_kernel", "sepdense_prep_kernel", "sepdense_block_kernel", "sepdense_trail_kernel")
 
 
 def summarize(path):
