@@ -1259,6 +1259,7 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   const Plan& P = h->plan;
   const int nsl = (int)P.st_lvl_ptr.size() - 1;
   HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 2 + (int64_t)a.ntasks, s));
+  HIPCHK(h, launch_solve_pending(Z, (int64_t)a.n * nrhs, s));
   HIPCHK(h, hipEventRecord(h->ev[2], s));
   if (h->opt.sched_flags & 4) {
     for (int l = 0; l < nsl; l++) {

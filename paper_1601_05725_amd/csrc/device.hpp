@@ -269,6 +269,8 @@ hipError_t launch_solve_tasks(const SolveArgs& a, int ntasks, hipStream_t s);
 hipError_t launch_solve_flow(const SolveArgs& a, int grid, hipStream_t s);
 // LDS the one-launch solve kernel declares itself; its dynamic LDS is the rest
 constexpr int kSolveFlowStaticLds = 256;
+// Z (cnt doubles) set to the pending pattern the solve's tasks wait on; before every solve
+hipError_t launch_solve_pending(double* Z, int64_t cnt, hipStream_t s);
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s);
 // the static device scratch of the solve that allocates nothing: its size in doubles,
 // and its address on a device (looked up once per device; the device must be current)

@@ -93,6 +93,65 @@ __device__ __forceinline__ double subtract_in_order(double acc, double prod, int
 
 // The first (up to) 64 entries of a sorted factor row, loaded ahead of their use: the
 // lane's column and value, and the row's entry range.
+// In the lane-per-row sweep a row's LDS value is its done flag: V holds kPending until
+// the row's result is stored there with one 64-bit access.  kPending is a signaling NaN,
+// which no arithmetic result equals; a result with exactly that bit pattern (only a
+// copied input can have it) is stored quieted.
+constexpr unsigned long long kPending = 0x7ff0dead5a5a5a5aull;
+
+__device__ __forceinline__ bool pending_load(const double* V, int i, double& v) {
+  const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(V) + i, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+  v = __longlong_as_double((long long)b);
+  return b != kPending;
+}
+
+__device__ __forceinline__ void result_store(double* V, int i, double z) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(z);
+  if (b == kPending) b |= 1ull << 51;
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(V) + i, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The solution vector Z is also a set of done flags, across workgroups: it holds
+// kPending before the solve, and every unknown is stored there once, final, by the
+// backward sweep that computes it, with one 64-bit store at agent scope (it reaches the
+// memory every XCD reads); a row of another task reads it with agent-scope loads until
+// the value is no longer kPending.  No fence is needed: the value is its own flag.
+__device__ __forceinline__ void publish_store(double* Zp, int i, double z) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(z);
+  if (b == kPending) b |= 1ull << 51;
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(Zp) + i, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool published_load(const double* Z, int j, double& v) {
+  const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(Z) + j, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  v = __longlong_as_double((long long)b);
+  return b != kPending;
+}
+
+// Bound of a wait for another task's results: 10 s of the 100 MHz real-time counter (a
+// producing task can legitimately run for tens of milliseconds), or less once another
+// wait of the launch has given up (status bit 8).
+constexpr unsigned long long kFlowWaitTicks = 1000000000ull;
+
+// Wait until Z[j] is published; false (and status bit 8 set) when the wait gave up.
+__device__ __noinline__ bool wait_published(const SolveArgs& a, const double* Z, int j, double& v) {
+  const unsigned long long w0 = __builtin_amdgcn_s_memrealtime();
+  unsigned spins = 0;
+  while (!published_load(Z, j, v)) {
+    __builtin_amdgcn_s_sleep(2);
+    if ((++spins & 255u) == 0 &&
+        (__builtin_amdgcn_s_memrealtime() - w0 > kFlowWaitTicks ||
+         (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8))) {
+      __hip_atomic_fetch_or(a.status, 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      v = 0.0;
+      return false;
+    }
+  }
+  return true;
+}
+
 struct RowPre {
   int e0, e1;
   int j;
@@ -167,7 +226,7 @@ constexpr int kPre = 4;
 template <bool kLds, bool kBack>
 __device__ __forceinline__ bool sweep(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O, int ooff,
                                       const unsigned long long* keys, const double* vals, const Flags<kLds>& F,
-                                      const double* fin, int r0, int m, int wv, int lane) {
+                                      const double* fin, double* Zp, int r0, int m, int wv, int lane) {
   const int n = a.n;
   RowPre pre[kPre];
   int kr[kPre];
@@ -192,7 +251,10 @@ __device__ __forceinline__ bool sweep(const SolveArgs& a, double* V, const int32
         double acc = V[kr[i]];
         ok &= row_update<kLds>(acc, pre[i], keys, vals, kBack, n, r0, m, V, F, fin, lane);
         if (kBack) acc = acc / dg[i];
-        if (lane == 0) V[kr[i]] = acc;
+        if (lane == 0) {
+          V[kr[i]] = acc;
+          if (kBack) publish_store(Zp, kr[i], acc);
+        }
         publish_fence<kLds>();
         if (lane == 0) F.set(kr[i]);
         const int qn = q + kPre * kSW;
@@ -310,25 +372,6 @@ __device__ __forceinline__ void apply_prefixes(const SolveArgs& a, double* G, co
   }
 }
 
-// In the lane-per-row sweep a row's LDS value is its done flag: V holds kPending until
-// the row's result is stored there with one 64-bit access.  kPending is a signaling NaN,
-// which no arithmetic result equals; a result with exactly that bit pattern (only a
-// copied input can have it) is stored quieted.
-constexpr unsigned long long kPending = 0x7ff0dead5a5a5a5aull;
-
-__device__ __forceinline__ bool pending_load(const double* V, int i, double& v) {
-  const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(V) + i, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-  v = __longlong_as_double((long long)b);
-  return b != kPending;
-}
-
-__device__ __forceinline__ void result_store(double* V, int i, double z) {
-  unsigned long long b = (unsigned long long)__double_as_longlong(z);
-  if (b == kPending) b |= 1ull << 51;
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(V) + i, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // The sweep with one row per thread, for tasks in LDS whose rows are short: 64 kSW rows
 // in flight.  The wavefronts work in rounds: in round r lane i of wave w takes position
 // r 64 kSW + 64 w + i of the issue order, and the wave moves to its next round once all
@@ -341,7 +384,7 @@ __device__ __forceinline__ void result_store(double* V, int i, double z) {
 template <bool kBack>
 __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
                                             const unsigned long long* keys, const double* vals, const double* A0,
-                                            const Slots& S, int r0, int m, int tid) {
+                                            const Slots& S, double* Zp, int r0, int m, int tid) {
   constexpr int T = 64 * kSW;
   const int n = a.n;
   RowRegs nx;
@@ -413,7 +456,9 @@ __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const
           prog = c > 0;
         }
         if (p >= e1) {
-          result_store(V, kc, kBack ? acc / dg : acc);
+          const double z = kBack ? acc / dg : acc;
+          result_store(V, kc, z);
+          if (kBack) publish_store(Zp, kc, z);
           busy = false;
           prog = true;
         }
@@ -430,29 +475,32 @@ __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const
   return !stalled;
 }
 
-// Residual of task row kk: the right-hand side minus the coupling to finished later
-// blocks, in the sweep's order; the entries' loads are issued four at a time.
-__device__ __forceinline__ double residual_row(const SolveArgs& a, const double* Bc, const double* Z, int i) {
+// Residual of task row kk: the right-hand side minus the coupling to later blocks, in
+// the sweep's order; the entries' loads are issued four at a time, and an entry not yet
+// published is waited for.  ok turns false when a wait gave up.
+__device__ __forceinline__ double residual_row(const SolveArgs& a, const double* Bc, const double* Z, int i,
+                                               bool& ok) {
   double acc = Bc[a.prow[i]];
   int q = a.OTp[i];
   const int qe = a.OTp[i + 1];
-  for (; q + 4 <= qe; q += 4) {
-    const int j0 = a.OTj[q], j1 = a.OTj[q + 1], j2 = a.OTj[q + 2], j3 = a.OTj[q + 3];
-    const double x0 = a.OTx[q], x1 = a.OTx[q + 1], x2 = a.OTx[q + 2], x3 = a.OTx[q + 3];
-    const double z0 = Z[j0], z1 = Z[j1], z2 = Z[j2], z3 = Z[j3];
-    acc = acc - x0 * z0;
-    acc = acc - x1 * z1;
-    acc = acc - x2 * z2;
-    acc = acc - x3 * z3;
-  }
-  if (q < qe) {
+  for (; q < qe; q += 4) {
     const int c = qe - q;
-    const int j0 = a.OTj[q], j1 = c > 1 ? a.OTj[q + 1] : 0, j2 = c > 2 ? a.OTj[q + 2] : 0;
-    const double x0 = a.OTx[q], x1 = c > 1 ? a.OTx[q + 1] : 0.0, x2 = c > 2 ? a.OTx[q + 2] : 0.0;
-    const double z0 = Z[j0], z1 = c > 1 ? Z[j1] : 0.0, z2 = c > 2 ? Z[j2] : 0.0;
-    acc = acc - x0 * z0;
-    if (c > 1) acc = acc - x1 * z1;
-    if (c > 2) acc = acc - x2 * z2;
+    int j[4];
+    double x[4], z[4];
+    bool r[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      j[t] = t < c ? a.OTj[q + t] : 0;
+      x[t] = t < c ? a.OTx[q + t] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++) r[t] = t >= c || published_load(Z, j[t], z[t]);
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+      if (!r[t]) ok &= wait_published(a, Z, j[t], z[t]);
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+      if (t < c) acc = acc - x[t] * z[t];
   }
   return acc;
 }
@@ -466,7 +514,7 @@ __device__ __forceinline__ double residual_row(const SolveArgs& a, const double*
 template <bool kBack>
 __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
                                              const int32_t* Ej, const double* Ex, int e_base, const double* A0,
-                                             int r0, int m, int tid) {
+                                             double* Zp, int r0, int m, int tid) {
   constexpr int T = 64 * kSW;
   // the next round's row, a round ahead: task-local row, entry range, initial value, diagonal
   int nk = -1, ne0 = 0, ne1 = 0;
@@ -538,7 +586,9 @@ __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, cons
         nxt.x3 = Ex[at(p + 3)];
         prog = c > 0;
         if (p >= e1) {
-          result_store(V, kc, kBack ? acc / dg : acc);
+          const double z = kBack ? acc / dg : acc;
+          result_store(V, kc, z);
+          if (kBack) publish_store(Zp, kc, z);
           busy = false;
           prog = true;
         }
@@ -603,12 +653,13 @@ __host__ __device__ constexpr int64_t lds_slot_bytes() { return 12 * (int64_t)kS
 // One sweep (L forward, or U backward) of a task over its rows.  V holds the initial
 // values and receives the results.  P / O: the row pointers and issue order (LDS for a
 // task in LDS, else global with O offset by r0); `fin` the final values of columns
-// outside the task.
+// outside the task; Zp the task's rows of Z, where the backward sweep publishes each
+// result (null for the forward sweep).
 template <bool kLds, bool kBack>
 __device__ __forceinline__ bool run_sweep(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O, int ooff,
                                           char* R, int64_t rbytes, const Flags<kLds>& F, const unsigned long long* keys,
-                                          const double* vals, const double* fin, double* G, bool prefix, int r0, int m,
-                                          int tid) {
+                                          const double* vals, const double* fin, double* G, bool prefix, double* Zp,
+                                          int r0, int m, int tid) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
   if constexpr (kLds) {
@@ -631,14 +682,14 @@ __device__ __forceinline__ bool run_sweep(const SolveArgs& a, double* V, const i
         int32_t* Ej = reinterpret_cast<int32_t*>(Ex + E);
         stage_entries<kBack>(Ej, Ex, keys, vals, e_base, E, r0, m, a.n, tid);
         __syncthreads();
-        return sweep_staged<kBack>(a, V, P, O, Ej, Ex, e_base, G, r0, m, tid);
+        return sweep_staged<kBack>(a, V, P, O, Ej, Ex, e_base, G, Zp, r0, m, tid);
       }
       double* Sx = reinterpret_cast<double*>(R);
       int32_t* Sj = reinterpret_cast<int32_t*>(Sx + kSlot * 64 * kSW);
-      return sweep_lanes<kBack>(a, V, P, O, keys, vals, G, Slots{Sj, Sx}, r0, m, tid);
+      return sweep_lanes<kBack>(a, V, P, O, keys, vals, G, Slots{Sj, Sx}, Zp, r0, m, tid);
     }
   }
-  return sweep<kLds, kBack>(a, V, P, O, ooff, keys, vals, F, fin, r0, m, wv, lane);
+  return sweep<kLds, kBack>(a, V, P, O, ooff, keys, vals, F, fin, Zp, r0, m, wv, lane);
 }
 
 // Pl: LDS row pointers (m + 1), Po: LDS issue order (m), R: the LDS region of the
@@ -657,9 +708,10 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
   const int obad = a.obad[r0];
   bool ok = true;
   if (kind != 2) {
-    // residual of every row (independent of the task's other rows)
+    // residual of every row (independent of the task's other rows; it waits only for
+    // the entries of later blocks it reads)
     F.clear(m, tid);
-    for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = residual_row(a, Bc, Z, a.piv[r0 + kk]);
+    for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = residual_row(a, Bc, Z, a.piv[r0 + kk], ok);
     // the task's L row pointers and forward order
     const int32_t* LP = a.LTp + r0;
     const int32_t* ord = (obad & 1) == 0 ? a.sfo + r0 : nullptr;
@@ -674,15 +726,15 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
       }
     }
     __syncthreads();
-    ok &= run_sweep<kLds, false>(a, V, LP, ord, ooff, R, rbytes, F, a.lkeys, a.lvals, W, W + r0, kind == 1, r0, m,
-                                 tid);
+    ok &= run_sweep<kLds, false>(a, V, LP, ord, ooff, R, rbytes, F, a.lkeys, a.lvals, W, W + r0, kind == 1, nullptr,
+                                 r0, m, tid);
     __syncthreads();
     if (kind == 1) {
       for (int kk = tid; kk < m; kk += 64 * kSW) W[r0 + kk] = V[kk];
       if (!ok && tid == 0) atomicOr(a.status, 4);
       return;
     }
-  } else {
+  } else if (V != W + r0) {
     for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = W[r0 + kk];
   }
   // U rows: z_k = (w_k - sum_{j > k} u_kj z_j) / u_kk
@@ -701,9 +753,9 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
     }
   }
   __syncthreads();
-  ok &= run_sweep<kLds, true>(a, V, UP, ord, ooff, R, rbytes, F, a.ukeys, a.uvals, Z, W + r0, kind == 2, r0, m, tid);
-  __syncthreads();
-  for (int kk = tid; kk < m; kk += 64 * kSW) Z[r0 + kk] = V[kk];
+  // every result is published to Z by the sweep as it is computed
+  ok &= run_sweep<kLds, true>(a, V, UP, ord, ooff, R, rbytes, F, a.ukeys, a.uvals, Z, W + r0, kind == 2, Z + r0, r0,
+                              m, tid);
   if (!ok && tid == 0) atomicOr(a.status, 4);
 }
 
@@ -724,8 +776,9 @@ __device__ __forceinline__ void solve_task_body(const SolveArgs& a, double* smem
     } else {
       const int r0 = kind == 0 ? a.blkptr[id] : a.grpptr[id];
       Flags<false> F{nullptr, a.sflag + r0};
-      // work vector in place: the block's (or node's) part of Z, or of W for a forward task
-      double* V = (kind == 1 ? a.W : a.Z) + (int64_t)rhs * a.n + r0;
+      // work vector in place: the block's (or node's) part of W (Z receives only the
+      // final values, which other tasks wait for)
+      double* V = a.W + (int64_t)rhs * a.n + r0;
       run_task<false>(a, V, nullptr, nullptr, nullptr, 0, F, kind, id, rhs, tid);
     }
     __syncthreads();
@@ -739,9 +792,12 @@ __global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
 
 // All tasks in one launch.  Workgroups take tasks from a counter in launch order (a
 // topological order of the task graph) and wait for each task's predecessors' done
-// flags before running it.  Every predecessor sits earlier in the order, so it was
-// taken by a workgroup that is already running, and the earliest unfinished task never
-// waits: the waits end without any assumption about how many workgroups are resident.
+// flags before running it; the entries of later blocks that a residual reads are not
+// flagged tasks but waited for one by one in Z (published as each is computed), so a
+// task starts while the blocks it couples to are still finishing.  Every task a wait
+// depends on sits earlier in the order, so it was taken by a workgroup that is already
+// running, and the earliest unfinished task never waits: the waits end without any
+// assumption about how many workgroups are resident.
 // A task's results are released at agent scope before its flag (workgroups of one
 // launch run on different XCDs, whose L2 caches are not coherent) and acquired at agent
 // scope after the wait.  Waits are also bounded, by elapsed time (the 100 MHz real-time
@@ -750,7 +806,6 @@ __global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
 // the bound sets bit 8 of the status, and every other wait sees that bit within 256
 // polls and gives up too, so a launch whose flags never arrive still ends (the solve
 // then reports the stall).
-constexpr unsigned long long kFlowWaitTicks = 1000000000ull;   // 10 s at 100 MHz
 // s_waitcnt operand: vector memory count 0, the export and LDS counts left free
 constexpr int kWaitVmcnt0 = 0x0F70;
 
@@ -800,6 +855,12 @@ __global__ void __launch_bounds__(64 * kSW) solve_flow_kernel(SolveArgs a) {
     __syncthreads();
     t = __builtin_amdgcn_readfirstlane(sh_t);
   }
+}
+
+// Z before a solve: every unknown pending
+__global__ void solve_pending_kernel(unsigned long long* Z, int64_t cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) Z[i] = kPending;
 }
 
 __global__ void solve_unpermute_kernel(SolveArgs a) {
@@ -852,6 +913,13 @@ hipError_t noalloc_scratch(int device, double** ptr) {
   }
   *ptr = it->second;
   return hipSuccess;
+}
+
+hipError_t launch_solve_pending(double* Z, int64_t cnt, hipStream_t s) {
+  if (cnt > 0)
+    hipLaunchKernelGGL(solve_pending_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(Z), cnt);
+  return hipGetLastError();
 }
 
 hipError_t launch_solve_finish(const SolveArgs& a, hipStream_t s) {

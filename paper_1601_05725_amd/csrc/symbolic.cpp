@@ -960,19 +960,14 @@ void build_solve_tasks(Plan& P) {
     P.st_need[q] = m;
     (kind[t] == 0 ? pos0[id[t]] : kind[t] == 1 ? pos1[id[t]] : pos2[id[t]]) = q;
   }
-  // Predecessors of every task (queue positions, all earlier in the queue): the tasks
-  // that produce the solution entries its residual reads through the off-diagonal
-  // blocks (a whole block's task, or the backward task of the ND node holding the
-  // column), an ND node's forward tasks of its children, and for a backward task its own
-  // forward task and its parent's backward task.
-  std::vector<int32_t> cgrp(n, -1);
-  for (int g = 0; g < ng; g++)
-    for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) cgrp[k] = g;
-  auto producer = [&](int k) { return is_nd[blk[k]] ? pos2[cgrp[k]] : pos0[blk[k]]; };
-  auto owner = [&](int i) { return is_nd[blk[i]] ? pos1[cgrp[i]] : pos0[blk[i]]; };
+  // Flagged predecessors of every task (queue positions, all earlier in the queue): an
+  // ND node's forward tasks of its children, and for a backward task its own forward
+  // task and its parent's backward task.  The solution entries a residual reads through
+  // the off-diagonal blocks are waited for one by one on the device, not through their
+  // tasks' flags; their tasks (a whole block's, or the backward task of the ND node
+  // holding the column) are still earlier in the queue, since the levels above count
+  // those couplings.
   std::vector<std::vector<int32_t>> pred(nt);
-  for (int k = 0; k < n; k++)
-    for (int32_t q = P.Op[k]; q < P.Op[k + 1]; q++) pred[owner(P.Oi[q])].push_back(producer(k));
   for (int g = 0; g < ng; g++) {
     if (pos1[g] < 0) continue;
     const int p = P.grp_parent[g];
