@@ -103,7 +103,7 @@ struct basker_ctx {
   std::vector<float> tune_ms;
   // solve tasks, row-wise factors (rebuilt after every factorization), done flags
   DBuf<int32_t> st_kind, st_id, s_status, sflag, LTp, UTp;
-  DBuf<int32_t> st_dep_ptr, st_dep, st_succ;   // the one-launch solve's task graph
+  DBuf<int32_t> st_dep_ptr, st_dep, st_succ, st_issue;   // the one-launch solve's task graph
   DBuf<int32_t> sfo, sbo, sfo_pos, sbo_pos, row_task0, obad, ocount;   // solve issue orders and their check
   DBuf<unsigned long long> lkeys, lkeys_out, ukeys, ukeys_out;
   DBuf<double> lvals, lvals_out, uvals, uvals_out, diag;
@@ -360,7 +360,7 @@ static int64_t plan_device_bytes(const Plan& P, const basker_options& o) {
   add(4, n + 1); add(4, nnzo); add(4, nnzo);                       // OTp, OTj, OTmap
   add(4, n); add(4, n); add(4, nb + 1); add(4, ng + 1);            // prow, qcol, blkptr, grpptr
   add(4, nt); add(4, nt); add(4, 2 + nt); add(4, n); add(4, n + 1); add(4, n + 1);   // tasks, status, flags, row pointers
-  add(4, nt + 1); add(4, (int64_t)P.st_dep.size()); add(4, nt);                // the one-launch solve's task graph
+  add(4, nt + 1); add(4, (int64_t)P.st_dep.size()); add(4, nt); add(4, nt);    // the one-launch solve's task graph
   add(8, n);                                                                     // U's diagonal
   for (int t = 0; t < 6; t++) add(4, n);                                         // solve issue orders
   add(4, 1);
@@ -481,6 +481,7 @@ static basker_status upload_plan(basker_ctx* h) {
   HIPCHK(h, h->st_dep_ptr.upload(P.st_dep_ptr, s));
   HIPCHK(h, h->st_dep.upload(P.st_dep, s));
   HIPCHK(h, h->st_succ.upload(P.st_succ, s));
+  HIPCHK(h, h->st_issue.upload(P.st_issue, s));
   HIPCHK(h, h->sflag.reserve(n));
   HIPCHK(h, h->LTp.reserve(n + 1));
   HIPCHK(h, h->UTp.reserve(n + 1));
@@ -1255,7 +1256,7 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   a.qctr = h->s_status.p + 1;
   a.done = h->s_status.p + 2;
   a.ntasks = (int32_t)h->plan.st_kind.size();
-  a.dep_ptr = h->st_dep_ptr.p; a.dep = h->st_dep.p; a.succ = h->st_succ.p;
+  a.dep_ptr = h->st_dep_ptr.p; a.dep = h->st_dep.p; a.succ = h->st_succ.p; a.issue = h->st_issue.p;
   const Plan& P = h->plan;
   const int nsl = (int)P.st_lvl_ptr.size() - 1;
   HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 2 + (int64_t)a.ntasks, s));

@@ -180,6 +180,7 @@ struct SolveArgs {
   // one launch for all tasks: predecessors of every task (launch positions), whether a
   // later task waits for it, done flags and the task counter (zero before the launch)
   int32_t ntasks;
+  const int32_t* issue;    // the order in which tasks are taken (launch positions)
   const int32_t* dep_ptr;
   const int32_t* dep;
   const int32_t* succ;

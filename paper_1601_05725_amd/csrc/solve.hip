@@ -790,7 +790,7 @@ __global__ void __launch_bounds__(64 * kSW) solve_task_kernel(SolveArgs a) {
   solve_task_body(a, smem_d, a.t_begin + (int)blockIdx.x, (int)threadIdx.x);
 }
 
-// All tasks in one launch.  Workgroups take tasks from a counter in launch order (a
+// All tasks in one launch.  Workgroups take tasks from a counter in issue order (a
 // topological order of the task graph) and wait for each task's predecessors' done
 // flags before running it; the entries of later blocks that a residual reads are not
 // flagged tasks but waited for one by one in Z (published as each is computed), so a
@@ -820,8 +820,9 @@ __global__ void __launch_bounds__(64 * kSW) solve_flow_kernel(SolveArgs a) {
   // barriers, so the other threads reran the previous task without end.
   if (tid == 0) sh_t = atomicAdd(a.qctr, 1);
   __syncthreads();
-  int t = __builtin_amdgcn_readfirstlane(sh_t);
-  while (t < a.ntasks) {
+  int c = __builtin_amdgcn_readfirstlane(sh_t);
+  while (c < a.ntasks) {
+    const int t = __builtin_amdgcn_readfirstlane(a.issue[c]);
     if (tid < 64) {
       bool stalled = false;
       for (int e = a.dep_ptr[t] + tid; e < a.dep_ptr[t + 1]; e += 64) {
@@ -853,7 +854,7 @@ __global__ void __launch_bounds__(64 * kSW) solve_flow_kernel(SolveArgs a) {
       sh_t = atomicAdd(a.qctr, 1);
     }
     __syncthreads();
-    t = __builtin_amdgcn_readfirstlane(sh_t);
+    c = __builtin_amdgcn_readfirstlane(sh_t);
   }
 }
 

@@ -986,6 +986,31 @@ void build_solve_tasks(Plan& P) {
     P.st_dep.insert(P.st_dep.end(), v.begin(), v.end());
     P.st_dep_ptr[q + 1] = (int32_t)P.st_dep.size();
   }
+  // Issue order of the one-launch solve: longest remaining path first.  A task's bottom
+  // level is its weight (rows plus a fixed start cost) plus the largest bottom level of
+  // the tasks that wait for it, through a flag or through a coupled solution entry (the
+  // producer of the entry: a block's task, or the ND node's backward task).  Every
+  // predecessor has a strictly larger bottom level, so the descending sort is a
+  // topological order.
+  std::vector<int32_t> cgrp(n, -1);
+  for (int g = 0; g < ng; g++)
+    for (int k = P.grpptr[g]; k < P.grpptr[g + 1]; k++) cgrp[k] = g;
+  auto producer = [&](int k) { return is_nd[blk[k]] ? pos2[cgrp[k]] : pos0[blk[k]]; };
+  auto owner = [&](int i) { return is_nd[blk[i]] ? pos1[cgrp[i]] : pos0[blk[i]]; };
+  std::vector<std::vector<int32_t>> succ(nt);
+  for (int q = 0; q < nt; q++)
+    for (int e = P.st_dep_ptr[q]; e < P.st_dep_ptr[q + 1]; e++) succ[P.st_dep[e]].push_back(q);
+  for (int k = 0; k < n; k++)
+    for (int32_t e = P.Op[k]; e < P.Op[k + 1]; e++) succ[producer(k)].push_back(owner(P.Oi[e]));
+  std::vector<int64_t> bl(nt, 0);
+  for (int q = nt - 1; q >= 0; q--) {
+    int64_t mx = 0;
+    for (int32_t s2 : succ[q]) mx = std::max(mx, bl[s2]);
+    bl[q] = mx + P.st_need[q] + 16;
+  }
+  P.st_issue.resize(nt);
+  for (int q = 0; q < nt; q++) P.st_issue[q] = q;
+  std::stable_sort(P.st_issue.begin(), P.st_issue.end(), [&](int32_t x, int32_t y) { return bl[x] > bl[y]; });
 }
 
 void build_levels(Plan& P) {

@@ -72,8 +72,9 @@ struct Plan {
   std::vector<int32_t> st_kind, st_id, st_need, st_lvl_ptr;
   // predecessors of every task in launch order (earlier positions, ascending):
   // st_dep[st_dep_ptr[q] .. st_dep_ptr[q + 1]); st_succ[q] = 1 when a later task waits
-  // for q
-  std::vector<int32_t> st_dep_ptr, st_dep, st_succ;
+  // for q; st_issue: the order in which the one-launch solve takes the tasks (launch
+  // positions, a topological order of the task graph with its couplings)
+  std::vector<int32_t> st_dep_ptr, st_dep, st_succ, st_issue;
   // ND groups for the solve: first descendant group (postorder), ancestors root first
   // (sg_anc[sg_anc_ptr[g] .. sg_anc_ptr[g+1])), total rows of the strict ancestors
   // (sg_choff: also the offset of the group's rows in any descendant's buffer), and
