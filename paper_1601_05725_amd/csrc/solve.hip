@@ -281,11 +281,49 @@ struct Slots {
   double* Sx;
 };
 
+// The coupling entries of a block task's row still to subtract, when the row-per-thread
+// forward sweep takes them itself (Zr non-null): entries [q, qe) of the row in the
+// off-diagonal part, the next one's column and value.  The row then starts from its
+// right-hand side and needs none of its task's other rows' couplings to begin.
+struct ResCur {
+  int q, qe, j;
+  double x;
+};
+
+__device__ __forceinline__ void res_open(ResCur& c, const SolveArgs& a, const double* Zr, int r0, int kk) {
+  c.q = c.qe = 0;
+  c.j = 0;
+  c.x = 0.0;
+  if (Zr != nullptr && kk >= 0) {
+    const int i = a.piv[r0 + kk];
+    c.q = a.OTp[i];
+    c.qe = a.OTp[i + 1];
+    if (c.q < c.qe) {
+      c.j = a.OTj[c.q];
+      c.x = a.OTx[c.q];
+    }
+  }
+}
+
+// Subtract the next coupling entry if its value is published; true on progress.
+__device__ __forceinline__ bool res_step(ResCur& c, const SolveArgs& a, const double* Zr, double& acc) {
+  double z;
+  if (!published_load(Zr, c.j, z)) return false;
+  acc = acc - c.x * z;
+  c.q++;
+  if (c.q < c.qe) {
+    c.j = a.OTj[c.q];
+    c.x = a.OTx[c.q];
+  }
+  return true;
+}
+
 // A row's first kSlot entries in registers (loaded a round before their use).
 struct RowRegs {
   int k, e0, e1;
   double d;
   double acc;
+  ResCur rc;
   int j[kSlot];
   double x[kSlot];
 };
@@ -293,7 +331,7 @@ struct RowRegs {
 template <bool kBack>
 __device__ __forceinline__ void load_row_regs(RowRegs& R, const SolveArgs& a, const int32_t* P, const int32_t* O,
                                               const unsigned long long* keys, const double* vals, const double* A0,
-                                              int r0, int m, int q) {
+                                              const double* Zr, int r0, int m, int q) {
   R.k = -1;
   R.e0 = R.e1 = 0;
   R.d = 1.0;
@@ -305,6 +343,7 @@ __device__ __forceinline__ void load_row_regs(RowRegs& R, const SolveArgs& a, co
     R.acc = A0[R.k];
     if (kBack) R.d = a.diag[r0 + R.k];
   }
+  res_open(R.rc, a, Zr, r0, R.k);
 #pragma unroll
   for (int t = 0; t < kSlot; t++) {
     R.j[t] = 0;
@@ -384,11 +423,12 @@ __device__ __forceinline__ void apply_prefixes(const SolveArgs& a, double* G, co
 template <bool kBack>
 __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
                                             const unsigned long long* keys, const double* vals, const double* A0,
-                                            const Slots& S, double* Zp, int r0, int m, int tid) {
+                                            const Slots& S, double* Zp, const double* Zr, int r0, int m,
+                                            int tid) {
   constexpr int T = 64 * kSW;
   const int n = a.n;
   RowRegs nx;
-  load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, r0, m, tid);
+  load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, Zr, r0, m, tid);
   unsigned idle = 0;
   bool stalled = false;
   for (int q = tid; __any(q < m); q += T) {
@@ -397,6 +437,7 @@ __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const
     const int e1 = nx.e1;
     const double dg = nx.d;
     double acc = nx.acc;
+    ResCur rc = nx.rc;
     bool busy = kc >= 0;
     // the window: entries p and p + 1 of the row, the second only while it is in the
     // slots (lim: the last slot holding an entry)
@@ -414,10 +455,12 @@ __device__ __forceinline__ bool sweep_lanes(const SolveArgs& a, double* V, const
         x1 = nx.x[1];
       }
     }
-    load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, r0, m, q + T);
+    load_row_regs<kBack>(nx, a, P, O, keys, vals, A0, Zr, r0, m, q + T);
     while (__any(busy)) {
       bool prog = false;
-      if (busy) {
+      if (busy && rc.q < rc.qe) {
+        prog = res_step(rc, a, Zr, acc);
+      } else if (busy) {
         if (p < e1) {
           double v0 = 0.0, v1 = 0.0;
           const bool c0 = pending_load(V, j0 >= 0 ? j0 : 0, v0) || j0 < 0;
@@ -514,11 +557,13 @@ __device__ __forceinline__ double residual_row(const SolveArgs& a, const double*
 template <bool kBack>
 __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O,
                                              const int32_t* Ej, const double* Ex, int e_base, const double* A0,
-                                             double* Zp, int r0, int m, int tid) {
+                                             double* Zp, const double* Zr, int r0, int m, int tid) {
   constexpr int T = 64 * kSW;
-  // the next round's row, a round ahead: task-local row, entry range, initial value, diagonal
+  // the next round's row, a round ahead: task-local row, entry range, initial value,
+  // diagonal, coupling entries
   int nk = -1, ne0 = 0, ne1 = 0;
   double nacc = 0.0, nd = 1.0;
+  ResCur nrc;
   auto fetch = [&](int q) {
     nk = -1;
     if (q < m) {
@@ -528,6 +573,7 @@ __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, cons
       nacc = A0[nk];
       if (kBack) nd = a.diag[r0 + nk];
     }
+    res_open(nrc, a, Zr, r0, nk);
   };
   fetch(tid);
   unsigned idle = 0;
@@ -536,6 +582,7 @@ __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, cons
     const int kc = nk, e1 = ne1;
     int p = ne0;
     double acc = nacc;
+    ResCur rc = nrc;
     const double dg = nd;
     bool busy = kc >= 0;
     // the window: entries p .. p + 3 of the row (indices clamped into the row), in one
@@ -561,7 +608,10 @@ __device__ __forceinline__ bool sweep_staged(const SolveArgs& a, double* V, cons
     fetch(q + T);
     auto pass = [&](const Win& cur, Win& nxt) {
       bool prog = false;
-      if (busy) {
+      if (busy && rc.q < rc.qe) {
+        prog = res_step(rc, a, Zr, acc);
+        nxt = cur;
+      } else if (busy) {
         double v0 = 0.0, v1 = 0.0;
         const bool r0_ = pending_load(V, cur.j0 >= 0 ? cur.j0 : 0, v0) || cur.j0 < 0;
         const bool r1_ = pending_load(V, cur.j1 >= 0 ? cur.j1 : 0, v1) || cur.j1 < 0;
@@ -654,18 +704,25 @@ __host__ __device__ constexpr int64_t lds_slot_bytes() { return 12 * (int64_t)kS
 // values and receives the results.  P / O: the row pointers and issue order (LDS for a
 // task in LDS, else global with O offset by r0); `fin` the final values of columns
 // outside the task; Zp the task's rows of Z, where the backward sweep publishes each
-// result (null for the forward sweep).
+// result (null for the forward sweep); Zr non-null when V holds the right-hand sides
+// and the row-per-thread sweep subtracts each row's couplings (read from Zr) itself.
+// Whether a task in LDS sweeps one row per thread: E entries over m rows, rbytes of LDS
+// for the sweep.
+__device__ __forceinline__ bool lane_sweep(int E, int m, int64_t rbytes) {
+  return E <= kLaneMeanMax * m && (12 * (int64_t)E <= rbytes || lds_slot_bytes() <= rbytes);
+}
+
 template <bool kLds, bool kBack>
 __device__ __forceinline__ bool run_sweep(const SolveArgs& a, double* V, const int32_t* P, const int32_t* O, int ooff,
                                           char* R, int64_t rbytes, const Flags<kLds>& F, const unsigned long long* keys,
                                           const double* vals, const double* fin, double* G, bool prefix, double* Zp,
-                                          int r0, int m, int tid) {
+                                          const double* Zr, int r0, int m, int tid) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
   if constexpr (kLds) {
     const int e_base = P[0];
     const int E = P[m] - e_base;
-    if (E <= kLaneMeanMax * m && (12 * (int64_t)E <= rbytes || lds_slot_bytes() <= rbytes)) {
+    if (lane_sweep(E, m, rbytes)) {
       // one row per thread: initial values to G (the task's rows of W, free until the
       // task's results), LDS values to pending
       for (int kk = tid; kk < m; kk += 64 * kSW) {
@@ -682,11 +739,11 @@ __device__ __forceinline__ bool run_sweep(const SolveArgs& a, double* V, const i
         int32_t* Ej = reinterpret_cast<int32_t*>(Ex + E);
         stage_entries<kBack>(Ej, Ex, keys, vals, e_base, E, r0, m, a.n, tid);
         __syncthreads();
-        return sweep_staged<kBack>(a, V, P, O, Ej, Ex, e_base, G, Zp, r0, m, tid);
+        return sweep_staged<kBack>(a, V, P, O, Ej, Ex, e_base, G, Zp, Zr, r0, m, tid);
       }
       double* Sx = reinterpret_cast<double*>(R);
       int32_t* Sj = reinterpret_cast<int32_t*>(Sx + kSlot * 64 * kSW);
-      return sweep_lanes<kBack>(a, V, P, O, keys, vals, G, Slots{Sj, Sx}, Zp, r0, m, tid);
+      return sweep_lanes<kBack>(a, V, P, O, keys, vals, G, Slots{Sj, Sx}, Zp, Zr, r0, m, tid);
     }
   }
   return sweep<kLds, kBack>(a, V, P, O, ooff, keys, vals, F, fin, Zp, r0, m, wv, lane);
@@ -709,9 +766,15 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
   bool ok = true;
   if (kind != 2) {
     // residual of every row (independent of the task's other rows; it waits only for
-    // the entries of later blocks it reads)
+    // the entries of later blocks it reads).  A block task swept one row per thread
+    // leaves the couplings to the sweep, so that each row starts as soon as its own
+    // are published; an ND node's rows subtract them before their prefix entries.
+    const bool defer = kLds && kind == 0 && lane_sweep(a.LTp[r0 + m] - a.LTp[r0], m, rbytes);
     F.clear(m, tid);
-    for (int kk = tid; kk < m; kk += 64 * kSW) V[kk] = residual_row(a, Bc, Z, a.piv[r0 + kk], ok);
+    for (int kk = tid; kk < m; kk += 64 * kSW) {
+      const int i = a.piv[r0 + kk];
+      V[kk] = defer ? Bc[a.prow[i]] : residual_row(a, Bc, Z, i, ok);
+    }
     // the task's L row pointers and forward order
     const int32_t* LP = a.LTp + r0;
     const int32_t* ord = (obad & 1) == 0 ? a.sfo + r0 : nullptr;
@@ -727,7 +790,7 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
     }
     __syncthreads();
     ok &= run_sweep<kLds, false>(a, V, LP, ord, ooff, R, rbytes, F, a.lkeys, a.lvals, W, W + r0, kind == 1, nullptr,
-                                 r0, m, tid);
+                                 defer ? Z : nullptr, r0, m, tid);
     __syncthreads();
     if (kind == 1) {
       for (int kk = tid; kk < m; kk += 64 * kSW) W[r0 + kk] = V[kk];
@@ -754,8 +817,8 @@ __device__ void run_task(const SolveArgs& a, double* V, int32_t* Pl, int32_t* Po
   }
   __syncthreads();
   // every result is published to Z by the sweep as it is computed
-  ok &= run_sweep<kLds, true>(a, V, UP, ord, ooff, R, rbytes, F, a.ukeys, a.uvals, Z, W + r0, kind == 2, Z + r0, r0,
-                              m, tid);
+  ok &= run_sweep<kLds, true>(a, V, UP, ord, ooff, R, rbytes, F, a.ukeys, a.uvals, Z, W + r0, kind == 2, Z + r0,
+                              nullptr, r0, m, tid);
   if (!ok && tid == 0) atomicOr(a.status, 4);
 }
 
