@@ -1048,7 +1048,9 @@ void build_levels(Plan& P) {
     P.crit_cols += mx;
   }
   // work items over the non-dense segments of every level: item i covers
-  // lvl_seg[item_lo[i] .. item_hi[i])
+  // lvl_seg[item_lo[i] .. item_hi[i]).  First-level segments are gathered up to
+  // kItemCols columns an item; a separator (level >= 1) is an item of its own, since its
+  // columns each take a long reach and the separators of a level are independent.
   const int kItemCols = 64;
   P.item_lo.clear();
   P.item_hi.clear();
@@ -1057,9 +1059,10 @@ void build_levels(Plan& P) {
     int q0 = P.lvl_ptr[l];
     while (q0 < P.lvl_ptr[l + 1] && dense[P.lvl_seg[q0]]) q0++;
     int start = q0, acc = 0;
+    const int cap = l == 0 ? kItemCols : 1;
     for (int q = q0; q < P.lvl_ptr[l + 1]; q++) {
       const int sz = P.seg_c1[P.lvl_seg[q]] - P.seg_c0[P.lvl_seg[q]];
-      if (acc > 0 && (acc >= kItemCols || sz >= kItemCols)) {
+      if (acc > 0 && (acc >= cap || sz >= cap)) {
         P.item_lo.push_back(start); P.item_hi.push_back(q);
         start = q;
         acc = 0;
