@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="c4: HBM budget of the resident handles (GB)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default first-level schedule instead of timing the candidates before the run")
+    ap.add_argument("--nd-leaves", type=int, default=0, metavar="P",
+                    help="leaves of the ND tree of large blocks (power of two); the configurations "
+                         "name 16, and any other count is reported as a variant of the workload")
     ap.add_argument("--schedule", default="", metavar="BIN,WAVES",
                     help="fixed first-level schedule (bin edge, wavefronts per workgroup) instead of the "
                          "autotuner's pick, e.g. 128,8 (for counter runs that must repeat one schedule)")
@@ -238,6 +241,10 @@ def main():
 
     t = time.perf_counter()
     a, cfg, opts = make_workload(args.workload)
+    if args.nd_leaves and args.nd_leaves != opts.get("nd_leaves", 16):
+        opts = dict(opts, nd_leaves=args.nd_leaves)
+        cfg = dict(cfg, workload=cfg["workload"].replace("_nd16", "") + "_nd%d_variant" % args.nd_leaves,
+                   nd_leaves=args.nd_leaves)
     log("workload %s n=%d nnz=%d generated in %.1fs" % (cfg["workload"], a.n, a.nnz, time.perf_counter() - t))
     t = time.perf_counter()
     if args.schedule:
