@@ -191,6 +191,18 @@ def test_nd_block(bk, orc):
     assert inf["dense_seps"] + inf["sparse_seps"] == len(seps)
 
 
+@pytest.mark.parametrize("leaves", [16, 32, 64])
+def test_nd_block_leaf_counts(bk, orc, leaves):
+    # deeper ND trees (more leaves than the configurations' 16): smaller leaves, one more
+    # level of small sparse separators per doubling, each separator a work item of its own
+    a = synth.gen_mna(30000, seed=8)
+    h, order, ext = run_case(bk, orc, a, label="mna30k-nd%d" % leaves, nd_min_block=3000, nd_leaves=leaves)
+    inf = h.info()
+    assert inf["nd_blocks"] >= 1
+    assert inf["nlevels"] == leaves.bit_length()   # log2(leaves) separator levels + the first level
+    assert inf["sparse_seps"] > 0
+
+
 def test_large_block_without_nd(bk, orc):
     # one 11k-row block: its solve work vectors exceed LDS and live in global memory
     a = synth.gen_mna(12000, seed=6)
