@@ -854,8 +854,12 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     a.level = nlev + l;
     a.col_begin = P.lvl_col_ptr[l];
     a.col_end = refactor ? P.lvl_col_ptr[l] + P.lvl_dcol_cnt[l] : P.lvl_col_ptr[l + 1];
-    int grid = std::min(std::min(a.col_end - a.col_begin, h->grid), kNumCu);
-    if (grid > 0 && (e = launch_factor_sep_step1(a, grid, s)) != hipSuccess) return e;
+    // one wave a column, as many as are resident: the 4,096-slot table takes a CU's LDS
+    // for one wave, the 2,048-slot one fits two, for plans whose every column workspace
+    // (the symbolic bound, first steps included) stays within 3/4 of it
+    const bool s1small = P.sym_ok && P.sym_ws_max <= (int64_t)kLdsSlotsStep1Small / 4 * 3;
+    int grid = std::min(std::min(a.col_end - a.col_begin, h->grid), s1small ? 2 * kNumCu : kNumCu);
+    if (grid > 0 && (e = launch_factor_sep_step1(a, grid, s1small, s)) != hipSuccess) return e;
     a.level = l;
     grid = std::min(a.item_end - a.item_begin, kNumCu * 3);
     if (h->opt.max_grid > 0) grid = std::min(grid, h->opt.max_grid);

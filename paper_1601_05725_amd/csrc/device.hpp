@@ -20,6 +20,8 @@ constexpr int kWave = 64;
 constexpr int kLdsSlots = 512;        // per-wave LDS hash slots (power of two)
 constexpr int kLdsSlotsSep = 1024;    // larger table for separator columns (mode 2)
 constexpr int kLdsSlotsStep1 = 4096;  // the column-parallel first step of separator levels
+// its variant for workspaces of at most 3/4 of this table (two waves fit a CU's LDS)
+constexpr int kLdsSlotsStep1Small = 2048;
                                       // (one workgroup per CU: ~135 KB of LDS)
 constexpr int kWavesPerCu = 6;        // persistent-grid occupancy target
 constexpr int kNumCu = 256;
@@ -260,7 +262,9 @@ hipError_t launch_factor_coop(const FactorArgs& a, int waves, int grid, hipStrea
 // column marks k's item for the redo pass
 hipError_t launch_factor_spec_check(const FactorArgs& a, int ncols_level0, const int32_t* cols, hipStream_t s);
 int coop_lds_bytes(int waves);
-hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, hipStream_t s);
+// small: the kLdsSlotsStep1Small variant (two waves a CU), for plans whose column
+// workspaces are bounded by 3/4 of its table
+hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, bool small, hipStream_t s);
 hipError_t launch_factor_sep_step2(const FactorArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const double* vals, const int32_t* map, double* out, int64_t cnt, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t cnt, hipStream_t s);

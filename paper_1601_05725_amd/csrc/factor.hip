@@ -113,6 +113,7 @@ struct Ws {
   int NP;         // capacity of the pivotal list
   int shift;      // 32 - log2(H)
   int SC;         // capacity of the stage (entries)
+  int lim;        // rows a column may hold before it moves to the global workspace
 };
 
 // Per-wave pool allocator: a wave claims a chunk of the L and U pools with one atomic
@@ -164,7 +165,7 @@ __device__ __forceinline__ unsigned hash_of(int32_t r, int shift) {
 }
 
 // insert r; returns the slot and whether it is new; -1 when the table is full.
-// The overflow flag is raised once more than half of the slots are in use.
+// The overflow flag is raised once more than w.lim slots are in use.
 __device__ __forceinline__ int ws_insert(const Ws& w, int32_t r, bool* isnew) {
   unsigned h = hash_of(r, w.shift);
   const unsigned mask = (unsigned)w.H - 1u;
@@ -173,7 +174,7 @@ __device__ __forceinline__ int ws_insert(const Ws& w, int32_t r, bool* isnew) {
     if (old == -1) {
       int pos = atomicAdd(&w.cnt[0], 1);
       w.ins[pos] = (int32_t)h;
-      if (pos >= (w.H >> 1)) w.cnt[2] = 1;
+      if (pos >= w.lim) w.cnt[2] = 1;
       *isnew = true;
       return (int)h;
     }
@@ -451,7 +452,7 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
     // known pattern: U(:,k) rows (pivotal, ascending) and L(:,k) rows plus the pivot
     ub = a.Ubeg[k]; uc = a.Ucnt[k]; lb = a.Lbeg[k]; lc = a.Lcnt[k];
     p = a.piv[k];
-    if (uc - 1 + lc + 1 > (w.H >> 1)) return 1;
+    if (uc - 1 + lc + 1 > w.lim) return 1;
     for (int t = lane; t < uc - 1; t += 64) {
       const int32_t j = a.Ui[ub + t];
       bool isnew;
@@ -827,7 +828,9 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
   return 0;
 }
 
-template <int HS, int NPS>
+// HS hash slots and NPS pivotal-list entries per wave in LDS; a column moves to the
+// global workspace past LQ quarters of the table (open addressing stays short at 3/4).
+template <int HS, int NPS, int LQ = 2>
 __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   BASKER_SHARED(LdsWs<HS COMMA NPS>, lds);
   const int lane = lane_id();
@@ -842,6 +845,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
   wl.NP = NPS;
   wl.shift = 32 - __builtin_ctz(HS);
   wl.SC = kStage;
+  wl.lim = HS / 4 * LQ;
   Ws wg;
   {
     const int H = a.gws_slots;
@@ -862,6 +866,7 @@ __global__ void __launch_bounds__(64) factor_kernel(FactorArgs a) {
     wg.NP = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
     wg.SC = kStage;
+    wg.lim = H >> 1;
   }
   wsync();
   const ColCtx cx0 = {0, nullptr, 0};
@@ -998,6 +1003,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
   wl.NP = HS / 2;
   wl.shift = 32 - __builtin_ctz(HS);
   wl.SC = kCoopStage;
+  wl.lim = HS >> 1;
   Ws wg;
   {
     const int H = a.gws_slots;
@@ -1018,6 +1024,7 @@ __global__ void __launch_bounds__(64 * NW) factor_coop_kernel(FactorArgs a) {
     wg.NP = H;
     wg.shift = 32 - __builtin_ctz((unsigned)H);
     wg.SC = kCoopStage;
+    wg.lim = H >> 1;
   }
   Alloc al = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   long long sub_l = 0, sub_u = 0;
@@ -1352,8 +1359,11 @@ hipError_t launch_factor_spec_check(const FactorArgs& a, int ncols, const int32_
   return hipGetLastError();
 }
 
-hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((factor_kernel<kLdsSlotsStep1, kLdsSlotsStep1 / 2>), dim3(grid), dim3(64), 0, s, a);
+hipError_t launch_factor_sep_step1(const FactorArgs& a, int grid, bool small, hipStream_t s) {
+  if (small)
+    hipLaunchKernelGGL((factor_kernel<kLdsSlotsStep1Small, kLdsSlotsStep1Small / 2, 3>), dim3(grid), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((factor_kernel<kLdsSlotsStep1, kLdsSlotsStep1 / 2>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
