@@ -211,32 +211,38 @@ __device__ __forceinline__ void sep_run(const DenseSepArgs& a, int d, int lds_by
       for (int i = tid; i < W * nbk; i += kDT) Sb[i] = S[i + (int64_t)k0 * W];
       __syncthreads();
     // ---- factor the block column by column
+    const int nsw = m > 256 * (kNW - 1) ? kNW : (m + 255) / 256 > 0 ? (m + 255) / 256 : 1;   // searching waves
     for (int t = 0; t < nbk; t++) {
       const int k = k0 + t;
       const int c = c0 + k;
       double* Pk = Pb + (size_t)t * H;
       const unsigned long long* Sk = Sb + (size_t)t * W;
       // pivot search over the separator's non-pivotal rows (a structurally zero row
-      // holds an exact 0 and attains the maximum only in a singular column)
-      double best = -1.0;
-      int bidx = 0x7fffffff;
-      for (int i = tid; i < m; i += kDT) {
-        if (bit(piv_bits, i)) continue;
-        const double v = fabs(Pk[i]);
-        if (v > best || (v == best && i < bidx)) { best = v; bidx = i; }
-      }
+      // holds an exact 0 and attains the maximum only in a singular column), on one
+      // wave per 256 rows: the largest magnitude, the smallest row among equals, is the
+      // same however the rows are split, and fewer partial results are combined
+      if (wv < nsw) {
+        double best = -1.0;
+        int bidx = 0x7fffffff;
+        for (int i = wv * 64 + lane; i < m; i += nsw * 64) {
+          if (bit(piv_bits, i)) continue;
+          const double v = fabs(Pk[i]);
+          if (v > best || (v == best && i < bidx)) { best = v; bidx = i; }
+        }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bidx, o, 64);
-        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ob = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bidx, o, 64);
+          if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+        }
+        if (lane == 0) { red_v[wv] = best; red_i[wv] = bidx; }
       }
-      if (lane == 0) { red_v[wv] = best; red_i[wv] = bidx; }
       __syncthreads();
-      // every thread combines the waves' results in the same order: the same decision
+      // every thread combines the searching waves' results in the same order: the same
+      // decision
       double bm = -1.0;
       int bi = 0x7fffffff;
-      for (int u = 0; u < kNW; u++)
+      for (int u = 0; u < nsw; u++)
         if (red_v[u] > bm || (red_v[u] == bm && red_i[u] < bi)) { bm = red_v[u]; bi = red_i[u]; }
       const bool dcand = !bit(piv_bits, k) && bit(Sk, k);
       int p;
