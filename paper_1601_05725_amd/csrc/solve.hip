@@ -91,8 +91,6 @@ __device__ __forceinline__ double subtract_in_order(double acc, double prod, int
   return acc;
 }
 
-// The first (up to) 64 entries of a sorted factor row, loaded ahead of their use: the
-// lane's column and value, and the row's entry range.
 // In the lane-per-row sweep a row's LDS value is its done flag: V holds kPending until
 // the row's result is stored there with one 64-bit access.  kPending is a signaling NaN,
 // which no arithmetic result equals; a result with exactly that bit pattern (only a
@@ -136,7 +134,7 @@ __device__ __forceinline__ bool published_load(const double* Z, int j, double& v
 constexpr unsigned long long kFlowWaitTicks = 1000000000ull;
 
 // Wait until Z[j] is published; false (and status bit 8 set) when the wait gave up.
-__device__ __noinline__ bool wait_published(const SolveArgs& a, const double* Z, int j, double& v) {
+__device__ __forceinline__ bool wait_published(const SolveArgs& a, const double* Z, int j, double& v) {
   const unsigned long long w0 = __builtin_amdgcn_s_memrealtime();
   unsigned spins = 0;
   while (!published_load(Z, j, v)) {
@@ -152,6 +150,8 @@ __device__ __noinline__ bool wait_published(const SolveArgs& a, const double* Z,
   return true;
 }
 
+// The first (up to) 64 entries of a sorted factor row, loaded ahead of their use: the
+// lane's column and value, and the row's entry range.
 struct RowPre {
   int e0, e1;
   int j;
@@ -176,27 +176,41 @@ __device__ __forceinline__ void row_prefetch(RowPre& r, const int32_t* ptr, cons
 // Subtract a sorted factor row from acc: columns inside the task's rows [r0, r0 + m)
 // are read from V after their done bits, any other column is final and read from `fin`.
 // Returns false on a stall.
+// Subtract a sorted factor row from acc: columns inside the task's rows [r0, r0 + m)
+// are read from V after their done bits, any other column is final and read from `fin`.
+// A row longer than 64 entries is taken 64 at a time with two chunks of loads ahead:
+// while chunk c is subtracted, the final values of chunk c + 1 and the entries of
+// chunk c + 2 are in flight.  Returns false on a stall.
 template <bool kLds>
 __device__ __forceinline__ bool row_update(double& acc, const RowPre& r, const unsigned long long* keys,
                                            const double* vals, bool rev, int n, int r0, int m, const double* V,
                                            const Flags<kLds>& F, const double* fin, int lane) {
   bool stalled = false;
+  // chunk c (j0, x0, v0: the final value of an outside column), chunk c + 1 (j1, x1)
+  int j0 = r.j, j1 = -1;
+  double x0 = r.x, x1 = 0.0;
+  double v0 = (j0 >= 0 && (j0 < r0 || j0 >= r0 + m)) ? fin[j0] : 0.0;
+  if (r.e0 + 64 + lane < r.e1) {
+    const unsigned lo = (unsigned)keys[r.e0 + 64 + lane];
+    j1 = rev ? n - 1 - (int)lo : (int)lo;
+    x1 = vals[r.e0 + 64 + lane];
+  }
   for (int b = r.e0; b < r.e1; b += 64) {
     const int cnt = (r.e1 - b < 64) ? r.e1 - b : 64;
-    int j = r.j;
-    double x = r.x;
-    if (b != r.e0) {
-      j = -1;
-      if (lane < cnt) {
-        const unsigned lo = (unsigned)keys[b + lane];
-        j = rev ? n - 1 - (int)lo : (int)lo;
-        x = vals[b + lane];
+    int j2 = -1;
+    double x2 = 0.0, v1 = 0.0;
+    if (b + 64 < r.e1) {   // uniform
+      if (b + 128 + lane < r.e1) {
+        const unsigned lo = (unsigned)keys[b + 128 + lane];
+        j2 = rev ? n - 1 - (int)lo : (int)lo;
+        x2 = vals[b + 128 + lane];
       }
+      if (j1 >= 0 && (j1 < r0 || j1 >= r0 + m)) v1 = fin[j1];
     }
     double prod = 0.0;
     if (lane < cnt) {
-      double v;
-      const int jj = j - r0;
+      const int jj = j0 - r0;
+      double v = v0;
       if (jj >= 0 && jj < m) {
         unsigned spins = 0;
         while (!F.test(jj)) {
@@ -205,12 +219,15 @@ __device__ __forceinline__ bool row_update(double& acc, const RowPre& r, const u
         }
         consume_fence<kLds>();
         v = V[jj];
-      } else {
-        v = fin[j];
       }
-      prod = x * v;
+      prod = x0 * v;
     }
     acc = subtract_in_order(acc, prod, cnt);
+    j0 = j1;
+    x0 = x1;
+    v0 = v1;
+    j1 = j2;
+    x1 = x2;
   }
   return !__any(stalled);
 }
@@ -243,27 +260,29 @@ __device__ __forceinline__ bool sweep(const SolveArgs& a, double* V, const int32
     }
   }
   bool ok = true;
-  for (int q0 = wv; q0 < m; q0 += kPre * kSW) {
+  // the row in slot 0 is worked on; the others move down a slot after it, and the row
+  // kPre rows later is prefetched into the last slot (every slot index is static)
+  for (int q = wv; q < m; q += kSW) {
+    double acc = V[kr[0]];
+    ok &= row_update<kLds>(acc, pre[0], keys, vals, kBack, n, r0, m, V, F, fin, lane);
+    if (kBack) acc = acc / dg[0];
+    if (lane == 0) {
+      V[kr[0]] = acc;
+      if (kBack) publish_store(Zp, kr[0], acc);
+    }
+    publish_fence<kLds>();
+    if (lane == 0) F.set(kr[0]);
 #pragma unroll
-    for (int i = 0; i < kPre; i++) {
-      const int q = q0 + i * kSW;
-      if (q < m) {
-        double acc = V[kr[i]];
-        ok &= row_update<kLds>(acc, pre[i], keys, vals, kBack, n, r0, m, V, F, fin, lane);
-        if (kBack) acc = acc / dg[i];
-        if (lane == 0) {
-          V[kr[i]] = acc;
-          if (kBack) publish_store(Zp, kr[i], acc);
-        }
-        publish_fence<kLds>();
-        if (lane == 0) F.set(kr[i]);
-        const int qn = q + kPre * kSW;
-        if (qn < m) {
-          kr[i] = O ? O[qn] - ooff : (kBack ? m - 1 - qn : qn);
-          row_prefetch(pre[i], P, keys, vals, kr[i], kBack, n, lane);
-          if (kBack) dg[i] = a.diag[r0 + kr[i]];
-        }
-      }
+    for (int i = 0; i + 1 < kPre; i++) {
+      pre[i] = pre[i + 1];
+      kr[i] = kr[i + 1];
+      dg[i] = dg[i + 1];
+    }
+    const int qn = q + kPre * kSW;
+    if (qn < m) {
+      kr[kPre - 1] = O ? O[qn] - ooff : (kBack ? m - 1 - qn : qn);
+      row_prefetch(pre[kPre - 1], P, keys, vals, kr[kPre - 1], kBack, n, lane);
+      if (kBack) dg[kPre - 1] = a.diag[r0 + kr[kPre - 1]];
     }
   }
   return ok;
