@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cstdio>
@@ -110,6 +111,7 @@ struct basker_ctx {
   DBuf<char> rows_temp;
   std::vector<int32_t> st_lvl_lds;   // LDS bytes of every solve level's launch
   int32_t flow_lds = 0, flow_grid = 0;   // the one-launch solve: LDS per workgroup, workgroups
+  int32_t flow_grid_shared = 0;           // workgroups while other solves run on the device
   // numeric state
   DBuf<double> vals, Rx, OTx;
   DBuf<int32_t> pinv, piv, Lbeg, Lcnt, Ubeg, Ucnt, status;
@@ -517,12 +519,14 @@ static basker_status upload_plan(basker_ctx* h) {
       h->st_lvl_lds[l] = nt <= ncu ? lds_max : (int32_t)std::min<size_t>(need, (size_t)lds_max);
     }
     // one launch for every task: workgroups with the whole LDS of a CU (less the
-    // kernel's own few static bytes) on half the CUs -- the chain of dependent tasks
-    // needs few at a time, and the other half stays free for concurrent handles
-    // (measured on the batched-BTF workload: 256 workgroups cost a quarter of the
-    // throughput of four handles in flight, 32 slowed the single solve by a third)
+    // kernel's own few static bytes), on every CU while the solve is the device's only
+    // work, on half of them while other handles work (measured on the batched-BTF
+    // workload: every CU takes the lone solve 15.4 -> 14.8 ms but costs a fifth of the
+    // throughput of four handles in flight; 32 workgroups slowed the lone solve by a
+    // third)
     h->flow_lds = lds_max - kSolveFlowStaticLds;
-    h->flow_grid = std::min<int>((int)P.st_kind.size(), std::max(ncu / 2, 1));
+    h->flow_grid = std::min<int>((int)P.st_kind.size(), std::max(ncu, 1));
+    h->flow_grid_shared = std::min<int>((int)P.st_kind.size(), std::max(ncu / 2, 1));
   }
   const int64_t nnzd = (int64_t)P.Ri.size();
   HIPCHK(h, h->vals.reserve(P.nnz));
@@ -1173,6 +1177,23 @@ static basker_status plan_guard(basker_ctx* h) {
   return BASKER_OK;
 }
 
+// Handles busy in a factorization, refactorization or solve on each device (those calls
+// return after their work), to size the one-launch solve's grid: every CU for a solve
+// that is the device's only work, half of them when other handles are working.
+constexpr int kMaxDevices = 64;
+static std::atomic<int> g_busy[kMaxDevices];
+
+struct BusyScope {
+  std::atomic<int>* c;
+  explicit BusyScope(int dev) : c(dev >= 0 && dev < kMaxDevices ? &g_busy[dev] : nullptr) {
+    if (c) c->fetch_add(1);
+  }
+  ~BusyScope() {
+    if (c) c->fetch_sub(1);
+  }
+  bool alone() const { return !c || c->load() <= 1; }
+};
+
 extern "C" basker_status basker_factor(basker_handle h, const double* values, int32_t values_on_device) {
   if (!h || (!values && h->plan.nnz > 0)) return BASKER_ERR_INVALID;
   AcctScope acct(&h->dev_bytes, h->opt.hbm_budget);
@@ -1180,6 +1201,7 @@ extern "C" basker_status basker_factor(basker_handle h, const double* values, in
   if (g != BASKER_OK) return g;
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   HIPCHK(h, hipSetDevice(h->device));
+  BusyScope busy(h->device);
   basker_status r = stage_values(h, values, values_on_device);
   if (r != BASKER_OK) return r;
   return do_factor(h);
@@ -1191,6 +1213,7 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
   if (h->device < 0) return fail(h, BASKER_ERR_DEVICE, "handle was created for analysis only (device < 0)");
   if (!h->factored) return fail(h, BASKER_ERR_PATTERN, "refactor before a successful factor");
   HIPCHK(h, hipSetDevice(h->device));
+  BusyScope busy(h->device);
   int32_t st[ST_WORDS];
   unsigned long long poolc[3], nnzc[2];
   basker_status r = BASKER_OK;
@@ -1238,7 +1261,8 @@ extern "C" basker_status basker_refactor(basker_handle h, const double* values, 
 // The task launches of one solve on device-resident B (leading dimension ld) with the
 // work vectors W and Z (n * nrhs doubles each) given by the caller; the status word,
 // flags and row-wise factors are the handle's.  Enqueues only: allocates nothing.
-static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int32_t ld, double* W, double* Z) {
+static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int32_t ld, double* W, double* Z,
+                                   bool alone) {
   hipStream_t s = h->stream;
   SolveArgs a{};
   a.n = h->plan.n;
@@ -1275,7 +1299,7 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   } else {
     a.t_begin = 0;
     a.lds_bytes = h->flow_lds;
-    HIPCHK(h, launch_solve_flow(a, h->flow_grid, s));
+    HIPCHK(h, launch_solve_flow(a, alone ? h->flow_grid : h->flow_grid_shared, s));
   }
   HIPCHK(h, launch_solve_finish(a, s));
   HIPCHK(h, hipEventRecord(h->ev[3], s));
@@ -1313,7 +1337,8 @@ extern "C" basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, 
     dB = h->Bdev.p;
     ld = n;
   }
-  basker_status r = enqueue_solve(h, nrhs, dB, ld, h->W.p, h->Z.p);
+  BusyScope busy(h->device);
+  basker_status r = enqueue_solve(h, nrhs, dB, ld, h->W.p, h->Z.p, busy.alone());
   if (r != BASKER_OK) return r;
   if (!B_on_device)
     HIPCHK(h, hipMemcpy2DAsync(B, sizeof(double) * (size_t)ldb, h->Bdev.p, sizeof(double) * n, sizeof(double) * n,
@@ -1335,7 +1360,8 @@ extern "C" basker_status basker_solve_noalloc(basker_handle h, int32_t nrhs, dou
     return fail(h, BASKER_ERR_WORKSPACE,
                 "solve needs " + std::to_string(need) + " doubles of scratch (2 n nrhs); the static scratch holds " +
                     std::to_string(kNoAllocScratchDoubles));
-  basker_status r = enqueue_solve(h, nrhs, B, ldb, sp, sp + n * nrhs);
+  BusyScope busy(h->device);
+  basker_status r = enqueue_solve(h, nrhs, B, ldb, sp, sp + n * nrhs, busy.alone());
   if (r != BASKER_OK) return r;
   return finish_solve(h);
 }
