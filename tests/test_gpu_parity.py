@@ -397,8 +397,8 @@ def test_full_c2_bitwise(bk, orc):
 
 @pytest.mark.parametrize("max_grid,flags", [(1, 0), (37, 1), (0, 1)])
 def test_deterministic_under_schedule(bk, orc, max_grid, flags):
-    """Survey T12: other grid sizes and the reverse order of work items change which
-    workgroup factors what and when; the factors must not change by a bit."""
+    """Schedule determinism: other grid sizes and the reverse order of work items change
+    which workgroup factors what and when; the factors must not change by a bit."""
     inp = synth.gen_batched_btf(nblocks=300, big=4000, seed=7)
     a = inp.a
     h0 = bk.Handle.symbolic(a, bk.default_options(nd_min_block=2000, nd_leaves=4))
