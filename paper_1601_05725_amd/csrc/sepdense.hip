@@ -338,10 +338,29 @@ __device__ __forceinline__ void sep_run(const DenseSepArgs& a, int d, int lds_by
       lb = __shfl(lb, 0, 64);
       if (__shfl(bad, 0, 64)) continue;
       // U: descendant part from the first step, then s-internal ascending, then diagonal
+      // (the descendant part copied 256 entries at a time: four loads per lane in flight)
       const int off = a.cb_off[c];
-      for (int u = lane; u < dnp; u += 64) {
-        if (!a.refactor) a.Ui[ub + u] = a.cbI[off + u];
-        a.Ux[ub + u] = a.cbX[off + u];
+      for (int u0 = 0; u0 < dnp; u0 += 256) {
+        int32_t ci[4];
+        double cx[4];
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+          const int u = u0 + 64 * g + lane;
+          ci[g] = 0;
+          cx[g] = 0.0;
+          if (u < dnp) {
+            if (!a.refactor) ci[g] = a.cbI[off + u];
+            cx[g] = a.cbX[off + u];
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+          const int u = u0 + 64 * g + lane;
+          if (u < dnp) {
+            if (!a.refactor) a.Ui[ub + u] = ci[g];
+            a.Ux[ub + u] = cx[g];
+          }
+        }
       }
       int pos = dnp;
       for (int j0 = 0; j0 < k; j0 += 64) {
