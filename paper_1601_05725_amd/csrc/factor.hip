@@ -760,10 +760,25 @@ __device__ __forceinline__ int factor_column(const FactorArgs& a, const Ws& w, i
     al.unz += uc;
     al.lnz += lc;
     if (dnp) {
+      // the descendant part the first step parked, four loads per lane in flight
       const int off = a.cb_off[k];
-      for (int e = lane; e < dnp; e += 64) {
-        a.Ui[ub + e] = a.cbI[off + e];
-        a.Ux[ub + e] = a.cbX[off + e];
+      for (int e0 = 0; e0 < dnp; e0 += 256) {
+        int32_t ci[4];
+        double cx[4];
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+          const int e = e0 + 64 * g + lane;
+          ci[g] = e < dnp ? a.cbI[off + e] : 0;
+          cx[g] = e < dnp ? a.cbX[off + e] : 0.0;
+        }
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+          const int e = e0 + 64 * g + lane;
+          if (e < dnp) {
+            a.Ui[ub + e] = ci[g];
+            a.Ux[ub + e] = cx[g];
+          }
+        }
       }
     }
     for (int e = lane; e < np; e += 64) {
