@@ -78,6 +78,8 @@ typedef struct {
                               column waits for its column-elimination-tree children);
                               bit 2: solve with one launch per level of the task graph
                               instead of one launch for all tasks;
+                              bit 3: the separator first step on its 4,096-slot LDS table
+                              even where the 2,048-slot one (two waves a CU) would do;
                               results do not depend on any of them (checks of determinism) */
   int32_t item_cols;       /* first-level work items hold at least this many columns unless a
                               block or ND leaf is larger (0 = 256) */

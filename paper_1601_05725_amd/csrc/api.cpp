@@ -861,7 +861,8 @@ static hipError_t enqueue_factor(basker_ctx* h, int refactor) {
     // one wave a column, as many as are resident: the 4,096-slot table takes a CU's LDS
     // for one wave, the 2,048-slot one fits two, for plans whose every column workspace
     // (the symbolic bound, first steps included) stays within 3/4 of it
-    const bool s1small = P.sym_ok && P.sym_ws_max <= (int64_t)kLdsSlotsStep1Small / 4 * 3;
+    const bool s1small =
+        !(h->opt.sched_flags & 8) && P.sym_ok && P.sym_ws_max <= (int64_t)kLdsSlotsStep1Small / 4 * 3;
     int grid = std::min(std::min(a.col_end - a.col_begin, h->grid), s1small ? 2 * kNumCu : kNumCu);
     if (grid > 0 && (e = launch_factor_sep_step1(a, grid, s1small, s)) != hipSuccess) return e;
     a.level = l;

@@ -203,6 +203,19 @@ def test_nd_block_leaf_counts(bk, orc, leaves):
     assert inf["sparse_seps"] > 0
 
 
+def test_first_step_tables_agree(bk, orc):
+    # the separator first step on the 2,048-slot table (two waves a CU, chosen when the
+    # symbolic workspace bound fits 3/4 of it) and on the 4,096-slot table (sched_flags
+    # bit 3): the same factors, bit for bit, and the oracle's
+    a = synth.gen_mna(30000, seed=8)
+    h0, order, ext0 = run_case(bk, orc, a, label="mna30k-nd32-step1-2048", nd_min_block=3000, nd_leaves=32)
+    h1, _, ext1 = run_case(bk, orc, a, order=order, label="mna30k-nd32-step1-4096", nd_min_block=3000,
+                           nd_leaves=32, sched_flags=8)
+    assert h0.info()["sym_ws_rows"] <= 1536
+    for key in ("piv", "Lp", "Li", "Lx", "Up", "Ui", "Ux"):
+        np.testing.assert_array_equal(getattr(ext0, key), getattr(ext1, key), err_msg=key)
+
+
 def test_large_block_without_nd(bk, orc):
     # one 11k-row block: its solve work vectors exceed LDS and live in global memory
     a = synth.gen_mna(12000, seed=6)
