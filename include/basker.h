@@ -80,6 +80,10 @@ typedef struct {
                               instead of one launch for all tasks;
                               bit 3: the separator first step on its 4,096-slot LDS table
                               even where the 2,048-slot one (two waves a CU) would do;
+                              bit 4 (a check of the failure path): the one-launch solve
+                              starts with its abort bit set, so each wait that has to
+                              wait gives up at once and the solve reports
+                              BASKER_ERR_DEVICE; the kernels still end normally;
                               results do not depend on any of them (checks of determinism) */
   int32_t item_cols;       /* first-level work items hold at least this many columns unless a
                               block or ND leaf is larger (0 = 256) */

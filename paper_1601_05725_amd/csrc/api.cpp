@@ -1289,6 +1289,9 @@ static basker_status enqueue_solve(basker_ctx* h, int32_t nrhs, double* dB, int3
   const Plan& P = h->plan;
   const int nsl = (int)P.st_lvl_ptr.size() - 1;
   HIPCHK(h, launch_fill_i32(h->s_status.p, 0, 2 + (int64_t)a.ntasks, s));
+  // sched_flags bit 4 (a check of the failure path): the launch starts as if a wait had
+  // already given up, so every wait that has to wait gives up at its first failed poll
+  if (h->opt.sched_flags & 16) HIPCHK(h, launch_fill_i32(h->s_status.p, 8, 1, s));
   HIPCHK(h, launch_solve_pending(Z, (int64_t)a.n * nrhs, s));
   HIPCHK(h, hipEventRecord(h->ev[2], s));
   if (h->opt.sched_flags & 4) {

@@ -130,7 +130,8 @@ __device__ __forceinline__ bool published_load(const double* Z, int j, double& v
 
 // Bound of a wait for another task's results: 10 s of the 100 MHz real-time counter (a
 // producing task can legitimately run for tens of milliseconds), or less once another
-// wait of the launch has given up (status bit 8).
+// wait of the launch has given up (status bit 8, read at a wait's first failed poll and
+// every 256 polls after it).
 constexpr unsigned long long kFlowWaitTicks = 1000000000ull;
 
 // Wait until Z[j] is published; false (and status bit 8 set) when the wait gave up.
@@ -139,7 +140,7 @@ __device__ __forceinline__ bool wait_published(const SolveArgs& a, const double*
   unsigned spins = 0;
   while (!published_load(Z, j, v)) {
     __builtin_amdgcn_s_sleep(2);
-    if ((++spins & 255u) == 0 &&
+    if ((++spins & 255u) == 1 &&
         (__builtin_amdgcn_s_memrealtime() - w0 > kFlowWaitTicks ||
          (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8))) {
       __hip_atomic_fetch_or(a.status, 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -913,7 +914,7 @@ __global__ void __launch_bounds__(64 * kSW) solve_flow_kernel(SolveArgs a) {
         const unsigned long long w0 = __builtin_amdgcn_s_memrealtime();
         while (__hip_atomic_load(&a.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
           __builtin_amdgcn_s_sleep(2);
-          if ((++spins & 255u) == 0 &&
+          if ((++spins & 255u) == 1 &&
               (__builtin_amdgcn_s_memrealtime() - w0 > kFlowWaitTicks ||
                (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8))) {
             stalled = true;

@@ -216,6 +216,25 @@ def test_first_step_tables_agree(bk, orc):
         np.testing.assert_array_equal(getattr(ext0, key), getattr(ext1, key), err_msg=key)
 
 
+def test_solve_abort_path_ends_and_reports(bk, orc):
+    # sched_flags bit 4 starts the one-launch solve with its abort bit set: every wait
+    # that has to wait (per-entry waits on coupled solution entries, ND task flags) gives
+    # up at its first failed poll, the launch still ends, and the solve reports the stall;
+    # a handle without the flag then solves bit for bit as the oracle does
+    inp = synth.gen_batched_btf(nblocks=300, big=4000, seed=7)
+    a = inp.a
+    b = synth.rhs(a.n, 1)
+    h_bad = bk.Handle.symbolic(a, bk.default_options(nd_min_block=2000, nd_leaves=4, sched_flags=16))
+    h_bad.factor(a.values)
+    say("abort-path solve, n=%d" % a.n)
+    with pytest.raises(bk.BaskerError) as ei:
+        h_bad.solve(b)
+    assert "did not end" in str(ei.value)
+    h_bad.free()
+    h, order, ext = run_case(bk, orc, a, label="after-abort", nd_min_block=2000, nd_leaves=4, nrhs=1)
+    assert h.info()["nd_blocks"] >= 1
+
+
 def test_large_block_without_nd(bk, orc):
     # one 11k-row block: its solve work vectors exceed LDS and live in global memory
     a = synth.gen_mna(12000, seed=6)
