@@ -87,7 +87,8 @@ typedef struct {
                               results do not depend on any of them (checks of determinism) */
   int32_t item_cols;       /* first-level work items hold at least this many columns unless a
                               block or ND leaf is larger (0 = 256) */
-  int32_t coop_waves;      /* wavefronts per workgroup of the first level: 4, 6 or 8 (0 = 6) */
+  int32_t coop_waves;      /* wavefronts per workgroup of the first level: 4, 6, 7 or 8 (0 = 6);
+                              4 to 7 waves have 512-slot LDS tables, 8 waves 256-slot ones */
   int32_t bin_edge;        /* size bins of the first level (Sec. III-B's fine BTF blocks): 1 x 1
                               blocks take one thread each, segments of 2..bin_edge columns one
                               wavefront each, larger ones share a workgroup's wavefronts

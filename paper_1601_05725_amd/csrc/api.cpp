@@ -176,7 +176,8 @@ static bool options_valid(const basker_options& o) {
   if (!(o.pivot_tol > 0.0 && o.pivot_tol <= 1.0)) return false;   // also rejects NaN
   if (o.nd_leaves < 1 || (o.nd_leaves & (o.nd_leaves - 1)) != 0) return false;
   if (o.hbm_budget < 0 || o.max_grid < 0 || o.item_cols < 0 || o.capacity_factor < 0) return false;
-  if (o.coop_waves != 0 && o.coop_waves != 4 && o.coop_waves != 6 && o.coop_waves != 8) return false;
+  if (o.coop_waves != 0 && o.coop_waves != 4 && o.coop_waves != 6 && o.coop_waves != 7 && o.coop_waves != 8)
+    return false;
   if (o.bin_edge < -1 || o.autotune < 0 || o.autotune > 1) return false;
   return true;
 }
@@ -1027,7 +1028,7 @@ struct TuneCand {
   int bin_edge;
   int waves;
 };
-constexpr TuneCand kTuneCands[] = {{32, 6}, {8, 6}, {128, 6}, {-1, 6}, {32, 8}, {128, 8}, {32, 4}};
+constexpr TuneCand kTuneCands[] = {{32, 6}, {8, 6}, {128, 6}, {-1, 6}, {32, 7}, {128, 7}, {32, 8}, {128, 8}, {32, 4}};
 constexpr int kNumTuneCands = (int)(sizeof(kTuneCands) / sizeof(kTuneCands[0]));
 
 // Rebuild the first level's work items for a bin edge and wave count and upload them;

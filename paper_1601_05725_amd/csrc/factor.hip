@@ -980,6 +980,7 @@ template <int NW>
 struct CoopCfg;
 template <> struct CoopCfg<4> { static constexpr int H = 512; };
 template <> struct CoopCfg<6> { static constexpr int H = 512; };
+template <> struct CoopCfg<7> { static constexpr int H = 512; };   // the most 512-slot waves a CU's LDS holds
 template <> struct CoopCfg<8> { static constexpr int H = 256; };
 
 // dependency lists of up to this many columns are copied to LDS for the checks
@@ -1352,6 +1353,7 @@ hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s) {
 int coop_lds_bytes(int waves) {
   if (waves == 4) return (int)sizeof(CoopLds<4>);
   if (waves == 6) return (int)sizeof(CoopLds<6>);
+  if (waves == 7) return (int)sizeof(CoopLds<7>);
   if (waves == 8) return (int)sizeof(CoopLds<8>);
   return 0;
 }
@@ -1362,6 +1364,8 @@ hipError_t launch_factor_coop(const FactorArgs& a, int waves, int grid, hipStrea
     hipLaunchKernelGGL(factor_coop_kernel<4>, dim3(grid), dim3(64 * 4), 0, s, a);
   else if (waves == 8)
     hipLaunchKernelGGL(factor_coop_kernel<8>, dim3(grid), dim3(64 * 8), 0, s, a);
+  else if (waves == 7)
+    hipLaunchKernelGGL(factor_coop_kernel<7>, dim3(grid), dim3(64 * 7), 0, s, a);
   else
     hipLaunchKernelGGL(factor_coop_kernel<6>, dim3(grid), dim3(64 * 6), 0, s, a);
   return hipGetLastError();

@@ -530,7 +530,7 @@ def test_speculation_redo_and_learning(bk, orc):
     assert orc.residual(a, h.solve(b), b) <= RES_TOL
 
 
-@pytest.mark.parametrize("waves,flags,item_cols", [(4, 0, 64), (8, 0, 1024), (6, 2, 256), (6, 3, 128)])
+@pytest.mark.parametrize("waves,flags,item_cols", [(4, 0, 64), (7, 0, 256), (8, 0, 1024), (6, 2, 256), (6, 3, 128)])
 def test_first_level_schedules_agree(bk, orc, waves, flags, item_cols):
     """Wavefronts per workgroup, item size, reverse item order and the safe-only
     schedule (flag 2) change who factors which column when; the factors stay the
