@@ -256,7 +256,7 @@ hipError_t launch_sepdense(const DenseSepArgs& a, int nsep, hipStream_t s);
 hipError_t launch_sepdense_split(const DenseSepArgs& a, int d, int H, int m, int ncu, hipStream_t s);
 hipError_t launch_factor_init(const FactorArgs& a, int32_t nlevels, hipStream_t s);
 hipError_t launch_factor_level(const FactorArgs& a, int grid, hipStream_t s);
-// first level on workgroups of `waves` wavefronts (4, 6 or 8); grid workgroups
+// first level on workgroups of `waves` wavefronts (4, 6, 7 or 8); grid workgroups
 hipError_t launch_factor_coop(const FactorArgs& a, int waves, int grid, hipStream_t s);
 // the speculation check after the first level: a row of L(:,k) pivoted by an earlier
 // column marks k's item for the redo pass

@@ -610,7 +610,7 @@ def test_autotune_keeps_the_factors(bk, orc):
         compare_exact(h.extract(), ref)
     say("trials %s -> bin edge %d, waves %d" % (trials, inf["sched_bin_edge"], inf["coop_waves"]))
     assert trials[0] == 0 and trials[-1] == max(trials) >= 6
-    assert inf["coop_waves"] in (4, 6, 8) and inf["sched_bin_edge"] in (0, 8, 32, 128)
+    assert inf["coop_waves"] in (4, 6, 7, 8) and inf["sched_bin_edge"] in (0, 8, 32, 128)
 
 
 @pytest.mark.gpu
