@@ -84,7 +84,7 @@ typedef struct {
                               starts with its abort bit set, so each wait that has to
                               wait gives up at once and the solve reports
                               BASKER_ERR_DEVICE; the kernels still end normally;
-                              results do not depend on any of them (checks of determinism) */
+                              bits 0-3 change no result (checks of determinism) */
   int32_t item_cols;       /* first-level work items hold at least this many columns unless a
                               block or ND leaf is larger (0 = 256) */
   int32_t coop_waves;      /* wavefronts per workgroup of the first level: 4, 6, 7 or 8 (0 = 6);
@@ -190,7 +190,10 @@ basker_status basker_refactor(basker_handle h, const double* values, int32_t val
 
 /* Solve A X = B in place for nrhs right-hand sides, column-major with leading
  * dimension ldb >= n (block back-substitution over the BTF form, Sec. II).  B is a
- * host pointer, or a device pointer when B_on_device != 0. */
+ * host pointer, or a device pointer when B_on_device != 0.  Returns after the solve.
+ * The solve is one launch over every CU of the device while no other handle of the
+ * process is inside basker_factor, basker_refactor or a solve on that device, over
+ * half of them otherwise; the result does not depend on it. */
 basker_status basker_solve(basker_handle h, int32_t nrhs, double* B, int32_t ldb, int32_t B_on_device);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
