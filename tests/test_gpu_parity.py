@@ -402,14 +402,16 @@ def test_exact_ties_integer(bk, orc, tau, dp, n, density, seed):
     run_case(bk, orc, a, order, tau=tau, diag_pref=dp, label="ties-%d-%d" % (n, seed), nrhs=1)
 
 
-def test_full_c2_bitwise(bk, orc):
+@pytest.mark.parametrize("waves,bin_edge", [(0, 0), (7, 128)])
+def test_full_c2_bitwise(bk, orc, waves, bin_edge):
     """The batched-BTF workload at full size (50,000 blocks + the 100k ND block, 16
-    leaves, n = 346,411), as the benchmark factors it: pivots, patterns and values bit
-    for bit against the oracle, dense separators included; solve residual."""
+    leaves, n = 346,411), as the benchmark factors it (the default schedule, and the
+    autotuner's usual pick: 7 waves, bin edge 128): pivots, patterns and values bit for
+    bit against the oracle, dense separators included; solve residual."""
     inp = synth.gen_batched_btf()
     a = inp.a
-    say("C2 full n=%d nnz=%d" % (a.n, a.nnz))
-    h = bk.Handle.symbolic(a, bk.default_options(nd_leaves=16))
+    say("C2 full n=%d nnz=%d waves %d bin edge %d" % (a.n, a.nnz, waves, bin_edge))
+    h = bk.Handle.symbolic(a, bk.default_options(nd_leaves=16, coop_waves=waves, bin_edge=bin_edge))
     prow, qcol, bp, gp = h.ordering()
     order = orc.Ordering(prow, qcol, bp, gp)
     h.factor(a.values)
