@@ -9,8 +9,10 @@
 //   backward task : the U rows of one ND node, root first (its rows depend on its own
 //                   rows and on its ancestors', finished earlier).
 // By default one launch runs every task (solve_flow_kernel): a workgroup takes the
-// tasks in launch order and waits on its predecessors' done flags; the launches per
-// level remain as an option.
+// tasks in an issue order, waits on the done flags of the ND tasks it depends on, and
+// waits for each coupled solution entry of a later block one by one (the solution
+// vector holds a pending pattern until the entry is published); the launches per level
+// remain as an option.
 // A task is one workgroup of kSW wavefronts.  The waves take the task's rows round
 // robin in an issue order, and a row waits only for the rows of the same task it reads
 // (done bits in LDS, release/acquire at workgroup scope).  The issue order of a
